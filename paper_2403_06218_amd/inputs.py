@@ -1,0 +1,107 @@
+"""Seeded synthetic inputs shared by the HIP path's tests, the benchmark and the oracle's checks.
+
+This module holds no arithmetic of the factorisation: it only draws numbers.
+The element stream is counter based, so any single row or column of a large
+matrix can be regenerated on the CPU without materialising the rest.
+
+Generator: SplitMix64 (Steele, Lea, Flood, "Fast splittable pseudorandom number
+generators", OOPSLA 2014), in the form of Vigna's public-domain reference
+``splitmix64.c``.  For seed ``s`` the stream state starts at
+``key = mix(s + GAMMA)`` and the element with linear index ``t`` is
+``z = mix(key + (t + 1) * GAMMA)`` (mod 2^64), i.e. output t of a SplitMix64
+stream seeded with ``key``.  A uniform double in [0, 1) is ``(z >> 11) * 2^-53``
+and a value in [lo, hi) is ``lo + (hi - lo) * u`` rounded as a product then a sum
+(exact for [-1, 1) and [-0.5, 0.5)).  Element (i, j) of a rows x cols matrix has
+linear index ``t = i + j * rows`` (column-major, independent of any padding).
+
+The HIP fill kernel in ``csrc/synth.hip`` implements the same definition
+independently, so a GPU-resident input of any size matches this module bit for bit.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def _mix(z: np.ndarray) -> np.ndarray:
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def stream_key(seed: int) -> np.uint64:
+    with np.errstate(over="ignore"):
+        return _mix(np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + GAMMA)[()]
+
+
+def uniform01(seed: int, idx) -> np.ndarray:
+    """Uniform doubles in [0, 1) for linear indices ``idx`` (any integer array)."""
+    key = stream_key(seed)
+    t = np.asarray(idx, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = _mix(key + (t + np.uint64(1)) * GAMMA)
+    return (z >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+def _affine(u: np.ndarray, lo: float, hi: float) -> np.ndarray:
+    scale = np.float64(hi) - np.float64(lo)
+    return np.float64(lo) + scale * u
+
+
+def uniform_matrix(rows: int, cols: int, seed: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    """rows x cols column-major (Fortran-order) float64 matrix of i.i.d. U[lo, hi)."""
+    out = np.empty((rows, cols), dtype=np.float64, order="F")
+    step = max(1, (1 << 24) // max(rows, 1))
+    for j0 in range(0, cols, step):
+        j1 = min(cols, j0 + step)
+        t = np.arange(j0 * rows, j1 * rows, dtype=np.uint64)
+        out[:, j0:j1] = _affine(uniform01(seed, t), lo, hi).reshape((j1 - j0, rows)).T
+    return out
+
+
+def uniform_rows(rows: int, cols: int, seed: int, row_idx, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    """Selected rows (len(row_idx) x cols) of ``uniform_matrix(rows, cols, seed)``."""
+    r = np.asarray(row_idx, dtype=np.uint64)[:, None]
+    c = np.arange(cols, dtype=np.uint64)[None, :]
+    return _affine(uniform01(seed, r + c * np.uint64(rows)), lo, hi)
+
+
+def uniform_cols(rows: int, cols: int, seed: int, col_idx, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    """Selected columns (rows x len(col_idx)) of ``uniform_matrix(rows, cols, seed)``."""
+    del cols
+    r = np.arange(rows, dtype=np.uint64)[:, None]
+    c = np.asarray(col_idx, dtype=np.uint64)[None, :]
+    return np.asfortranarray(_affine(uniform01(seed, r + c * np.uint64(rows)), lo, hi))
+
+
+def uniform_vector(n: int, seed: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    return _affine(uniform01(seed, np.arange(n, dtype=np.uint64)), lo, hi)
+
+
+def normal_matrix(rows: int, cols: int, seed: int) -> np.ndarray:
+    """Standard normal entries by Box-Muller on two counter streams (CPU only)."""
+    t = np.arange(rows * cols, dtype=np.uint64)
+    u1 = uniform01(seed, t)
+    u2 = uniform01(seed ^ 0x5DEECE66D, t)
+    z = np.sqrt(-2.0 * np.log1p(-u1)) * np.cos(2.0 * np.pi * u2)
+    return np.asfortranarray(z.reshape((cols, rows)).T)
+
+
+def diag_dominant(n: int, seed: int) -> np.ndarray:
+    """Off-diagonal U[-0.5, 0.5), diagonal = sum_{j != i} |a_ij| + 1 (row sums)."""
+    A = uniform_matrix(n, n, seed, -0.5, 0.5)
+    np.fill_diagonal(A, 0.0)
+    d = np.abs(A).sum(axis=1) + 1.0
+    A[np.arange(n), np.arange(n)] = d
+    return A
+
+
+def batch_sizes(count: int, lo: int, hi: int, seed: int) -> np.ndarray:
+    """``count`` integers drawn uniformly from [lo, hi] (inclusive)."""
+    u = uniform01(seed, np.arange(count, dtype=np.uint64))
+    return (lo + np.floor(u * (hi - lo + 1))).astype(np.int64)
