@@ -1,0 +1,133 @@
+/*
+ * cqr.h -- C ABI of libcqr.so: QR factorisation by block classical
+ * Gram-Schmidt with CholeskyQR2 re-orthogonalisation, on one AMD MI355X
+ * (gfx950), in IEEE double precision, and the linear solve from its factors.
+ *
+ * The operations follow Tomas, Quintana-Orti, Anzt, "Fast Truncated SVD of
+ * Sparse and Dense Matrices on Graphics Processors" (arXiv 2403.06218),
+ * Section 3 (Algorithms 3, 4 and 5 and Table 1).
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are column-major: element (i, j) of X with leading dimension
+ *     ldx is X[i + j * ldx].  Dimensions and leading dimensions are int64_t.
+ *   - Every matrix and vector pointer is a DEVICE pointer (hipMalloc'd or a
+ *     torch CUDA tensor), unless the parameter says "host".
+ *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *     All device work is enqueued on that stream, in stream order.
+ *   - The caller owns every buffer.  The library never allocates device
+ *     memory; scratch space is the caller's `work` buffer of at least the size
+ *     the matching *_workspace_size function returns (256-byte aligned).
+ *   - Return value: CQR_OK (0); -i if argument i (1-based position in the
+ *     C signature) is invalid; CQR_ERR_* below otherwise.  On an argument error
+ *     nothing is enqueued.
+ *   - Outputs of type int32_t* marked "host" are written by the host after the
+ *     call has synchronised the stream.
+ */
+#ifndef CQR_H
+#define CQR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CQR_OK 0
+#define CQR_ERR_UNSUPPORTED (-100) /* valid request this build does not support (b > 128, ld > 4e6) */
+#define CQR_ERR_WORKSPACE (-101)   /* work == NULL or work_bytes below the required size     */
+#define CQR_ERR_HIP_BASE (-1000)   /* -1000 - hipError_t: a HIP launch or runtime call failed */
+
+/* Bits of the per-block flags written by cqr_factor. */
+#define CQR_FLAG_FALLBACK 1 /* the block's Cholesky factorisation broke down; redone by CGS2 */
+#define CQR_FLAG_ZERO_COL 2 /* the block holds a column with no component outside the earlier ones */
+
+/* Human-readable text for a return code (static storage, never NULL). */
+const char* cqr_status_string(int code);
+
+/* Library version string (static storage). */
+const char* cqr_version(void);
+
+/*
+ * Bytes of device workspace cqr_factor needs for Y (q x r) and block width b;
+ * also valid for cqr_orth (r = b) and cqr_orth_against (r = s + b).
+ * Returns -1..-3 for q < 0, r < 0 or r > q, b < 1 or b > 128.
+ */
+int cqr_workspace_size(int64_t q, int64_t r, int64_t b, size_t* bytes);
+
+/*
+ * CGS-QR (Algorithm 3): Y (q x r, q >= r) = Q R with Q^T Q = I and R upper
+ * triangular with positive diagonal.  Q overwrites Y in place.
+ *   Y, ldy   in: Y; out: Q.  ldy >= max(1, q).
+ *   R, ldr   out: r x r upper triangular (strictly lower part set to 0).
+ *   b        block width, 1 <= b <= 128; the last block has width r - (k-1) b
+ *            with k = ceil(r / b).  Block 1 is orthogonalised by CholeskyQR2
+ *            (Algorithm 4); block j >= 2 by CGS-CQR2 (Algorithm 5) against the
+ *            s = (j-1) b columns before it, its projection written to
+ *            R[0:s, block j] and its triangular factor to the diagonal block.
+ *   work     device workspace of work_bytes >= cqr_workspace_size(q, r, b).
+ *   info     host, may be NULL: 0, or the 1-based index of the first block
+ *            whose Cholesky factorisation broke down (a pivot that is not > 0,
+ *            NaN included).  Such a block is restored and redone column by
+ *            column by classical Gram-Schmidt with re-orthogonalisation (CGS2),
+ *            which the paper's Section 3 prescribes as the fallback; the
+ *            result is still a QR factorisation.
+ *   block_flags  host, may be NULL, length k: CQR_FLAG_* bits per block.
+ *            A column whose remainder after projection has zero norm gets a
+ *            zero Q column and R_jj = 0 (CQR_FLAG_ZERO_COL).
+ * The call returns after the stream has finished the factorisation (it
+ * synchronises once at the end to learn whether a fallback is needed).
+ */
+int cqr_factor(int64_t q, int64_t r, int64_t b, double* Y, int64_t ldy, double* R, int64_t ldr, void* work,
+               size_t work_bytes, int32_t* info, int32_t* block_flags, void* stream);
+
+/*
+ * CholeskyQR2 (Algorithm 4): Q (q x b, q >= b) in place -> orthonormal Q and
+ * R (b x b upper triangular) with Q_in = Q_out R.  info (host, may be NULL):
+ * 0, or 1 if the fallback to CGS2 was taken.  Synchronises like cqr_factor.
+ */
+int cqr_orth(int64_t q, int64_t b, double* Q, int64_t ldq, double* R, int64_t ldr, void* work, size_t work_bytes,
+             int32_t* info, void* stream);
+
+/*
+ * CGS-CQR2 (Algorithm 5): orthogonalise Q (q x b) against P (q x s, whose
+ * columns are assumed orthonormal) ->  Q_in = P H + Q_out R, P^T Q_out = 0,
+ * Q_out^T Q_out = I.  H (s x b, ldh >= max(1, s)) and R (b x b) are outputs.
+ * Q and P must not overlap.  q >= s + b.  info as for cqr_orth.
+ */
+int cqr_orth_against(int64_t q, int64_t b, int64_t s, double* Q, int64_t ldq, const double* P, int64_t ldp,
+                     double* H, int64_t ldh, double* R, int64_t ldr, void* work, size_t work_bytes, int32_t* info,
+                     void* stream);
+
+/* Bytes of device workspace cqr_solve needs for order n (returns -1 for n < 0). */
+int cqr_solve_workspace_size(int64_t n, size_t* bytes);
+
+/*
+ * Solve Y x = rhs from the factors of cqr_factor for square Y (n x n):
+ * x = R^{-1} (Q^T rhs) -- a matrix-vector product then back substitution.
+ * (The paper does not solve systems; this is the factorisation's use.)
+ *   x        in: rhs (length n); out: the solution.
+ * A zero diagonal entry of R (a dependent column) yields Inf/NaN entries.
+ * Asynchronous: enqueues the work on `stream` and returns.
+ */
+int cqr_solve(int64_t n, const double* Q, int64_t ldq, const double* R, int64_t ldr, double* x, void* work,
+              size_t work_bytes, void* stream);
+
+/*
+ * Launch timing.  While enabled, every kernel launch the library makes is
+ * bracketed by a pair of hipEvents on its stream.  cqr_prof_query synchronises
+ * those events and returns, for the kernel role `name` (see cqr_prof_name),
+ * the number of launches, their summed duration in ms, and the summed
+ * algorithmic flop and byte counts of those launches (Table 1 cost model).
+ */
+int cqr_prof_enable(int on);
+int cqr_prof_reset(void);
+int cqr_prof_query(const char* name, int64_t* launches, double* total_ms, double* flops, double* bytes);
+/* Name of kernel role i (0-based), or NULL past the last one. */
+const char* cqr_prof_name(int i);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CQR_H */

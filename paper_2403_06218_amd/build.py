@@ -1,0 +1,50 @@
+"""Build the HIP libraries in-tree: lib/libcqr.so and lib/libcqr_synth.so (gfx950)."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(PKG, "csrc")
+LIBDIR = os.path.join(PKG, "lib")
+ROOT = os.path.dirname(PKG)
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+# Packed FP32 instructions are disabled for every HIP source.
+HIP_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-I" + os.path.join(ROOT, "include")]
+
+LIBS = {
+    "libcqr.so": ["cqr.hip", "gemm_f64.hip", "chol_f64.hip"],
+    "libcqr_synth.so": ["synth.hip"],
+}
+
+
+def _compile(out: str, sources: list[str], verbose: bool) -> None:
+    os.makedirs(LIBDIR, exist_ok=True)
+    target = os.path.join(LIBDIR, out)
+    tmp = target + ".tmp%d" % os.getpid()
+    cmd = [HIPCC] + HIP_FLAGS + ["-o", tmp] + [os.path.join(CSRC, s) for s in sources]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    # hipcc's host pass reports the disabled packed-fp32 feature as unknown; that is expected.
+    noise = "'-packed-fp32-ops' is not a recognized feature"
+    err = "\n".join(l for l in res.stderr.splitlines() if noise not in l)
+    if res.returncode != 0:
+        raise RuntimeError("hipcc failed for %s:\n%s" % (out, err))
+    if verbose and err.strip():
+        print(err, file=sys.stderr)
+    os.replace(tmp, target)
+
+
+def build(verbose: bool = False) -> None:
+    for out, sources in LIBS.items():
+        _compile(out, sources, verbose)
+
+
+if __name__ == "__main__":
+    build(verbose=True)

@@ -1,0 +1,68 @@
+// Internal declarations shared by the HIP sources of libcqr.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace cqr {
+
+// Kernel roles: each role is a distinct kernel symbol, so a profiler's
+// per-kernel statistics separate them, and the library's own launch timing
+// (cqr_prof_*) accumulates per role.
+enum Role : int {
+  ROLE_PROJ = 0,    // H = P^T Q        (Alg. 5 S1/S6)          TN GEMM, split-K
+  ROLE_UPDATE,      // Q = Q - P H      (Alg. 5 S2/S7)          NN GEMM
+  ROLE_GRAM,        // W = Q^T Q        (Alg. 4 S1/S4, 5 S3/S8) TN GEMM, split-K
+  ROLE_TRSM,        // Q = Q L^{-T}     (Alg. 4 S3/S6, 5 S5/S10) NN GEMM by (L^{-1})^T
+  ROLE_SMALL,       // R = Lb^T L^T, H += Hbar L^T (Alg. 5 S11/S12)
+  ROLE_REDUCE,      // split-K partial sums -> C
+  ROLE_CHOL,        // W = L L^T and L^{-1}  (Alg. 4 S2/S5, 5 S4/S9)
+  ROLE_COPY,        // block save / restore for the breakdown fallback
+  ROLE_GEMV,        // solve: c = Q^T rhs
+  ROLE_TRSV_DIAG,   // solve: diagonal-block back substitution
+  ROLE_TRSV_UPD,    // solve: off-diagonal update
+  ROLE_COUNT
+};
+
+const char* role_name(int role);
+
+// Launch timing hooks (no-ops unless cqr_prof_enable(1)).
+int prof_begin(hipStream_t s);
+void prof_end(int slot, int role, hipStream_t s, double flops, double bytes);
+
+// Split-K partial-sum buffer capacity chooser: returns the number of K splits
+// for a TN GEMM of M x N output and reduction length K, given the capacity of
+// the partial buffer in doubles.
+int choose_splits(int64_t M, int64_t N, int64_t K, size_t part_cap);
+
+// C = alpha * A^T B + beta * C;  A: K x M (lda), B: K x N (ldb), C: M x N (ldc).
+// Split over K through `part` (capacity part_cap doubles) when it pays.
+hipError_t gemm_tn(Role role, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+                   const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double* part,
+                   size_t part_cap, const int* gate, hipStream_t s, double flops);
+
+// C = alpha * A B + beta * C;  A: M x K (lda), B: K x N (ldb), C: M x N (ldc).
+// C may alias neither A nor B except element-wise (C(m,n) read only by its own update).
+hipError_t gemm_nn(Role role, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+                   const double* B, int64_t ldb, double beta, double* C, int64_t ldc, const int* gate,
+                   hipStream_t s, double flops);
+
+// Lower Cholesky W = L L^T of a b x b SPD matrix (b <= 128) and the inverse of
+// L, in one workgroup.  Writes LT = L^T and XT = (L^{-1})^T (both b x b,
+// leading dimension b, upper triangular with zero strictly-lower part).  On a
+// pivot that is not > 0 sets status[0] = code, status[1] = blk.
+hipError_t chol_inv(int b, const double* W, int64_t ldw, double* LT, double* XT, int* status, int code, int blk,
+                    hipStream_t s);
+
+// dst (rows x cols, ldd) = src (rows x cols, lds); gated on *gate == 0 when gate != NULL.
+hipError_t copy_matrix(int64_t rows, int64_t cols, const double* src, int64_t lds, double* dst, int64_t ldd,
+                       const int* gate, hipStream_t s);
+// X (rows x cols) = 0.
+hipError_t zero_matrix(int64_t rows, int64_t cols, double* X, int64_t ldx, hipStream_t s);
+
+// Solve kernels.
+hipError_t gemv_t(int64_t n, const double* Q, int64_t ldq, const double* x, double* y, hipStream_t s);
+hipError_t trsv_upper(int64_t n, const double* R, int64_t ldr, double* y, hipStream_t s);
+
+}  // namespace cqr

@@ -1,0 +1,188 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerances.  Both sides compute the unique thin QR with diag(R) > 0 through
+backward-stable steps, so by QR perturbation theory their factors differ by at
+most a small multiple of kappa_2(Y) * q * eps (relative to ||Y|| for R).  The
+tests use  |Q_gpu - Q_oracle| <= 8 kappa q eps  and
+|R_gpu - R_oracle| <= 8 kappa q eps ||Y||_2  element-wise, plus the backward
+error bars ||Y - QR||_F / (q eps ||Y||_F) < 16 and ||I - Q^T Q||_F / (q eps) < 16,
+and the HPL scaled residual < 16 for the solve.  The discrete outputs (info,
+per-block flags) must match the oracle bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2403_06218_amd as cqr
+from paper_2403_06218_amd import inputs
+from gpu_util import EPS, hpl_ratio, orth_ratio, recon_ratio, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+
+def _factor(Y, b, ld=None):
+    Yd = to_dev(Y, ld)
+    Q, R, info, flags = cqr.qr(Yd, b)
+    torch.cuda.synchronize()
+    return to_host(Q), to_host(R), info, flags
+
+
+def _compare(Y, b, Qg, Rg, info, flags, ref=None):
+    ref = ref or oracle.cgs_qr(Y, b)
+    q = Y.shape[0]
+    kappa = np.linalg.cond(Y)
+    tol = 8 * kappa * q * EPS
+    assert info == ref["info"]
+    assert list(flags) == list(ref["block_flags"])
+    np.testing.assert_allclose(Qg, ref["Q"], rtol=0, atol=tol)
+    np.testing.assert_allclose(Rg, ref["R"], rtol=0, atol=tol * np.linalg.norm(Y, 2))
+    assert np.array_equal(np.tril(Rg, -1), np.zeros_like(Rg))
+    assert (np.diag(Rg) > 0).all()
+    assert recon_ratio(Y, Qg, Rg) < 16
+    assert orth_ratio(Qg) < 16
+
+
+@pytest.mark.parametrize("b", [32, 64, 128])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_n512_uniform_factor_and_solve(b, seed):
+    """Plain FP64 workload at n = 512: entries U[-1, 1], one right-hand side."""
+    n = 512
+    Y = inputs.uniform_matrix(n, n, seed)
+    rhs = inputs.uniform_vector(n, seed + 1000)
+    Yd = to_dev(Y)
+    Qd, Rd, info, flags = cqr.qr(Yd, b)
+    xd = cqr.solve(Qd, Rd, torch.from_numpy(rhs).cuda())
+    torch.cuda.synchronize()
+    Qg, Rg, xg = to_host(Qd), to_host(Rd), xd.cpu().numpy()
+    ref = oracle.cgs_qr(Y, b)
+    _compare(Y, b, Qg, Rg, info, flags, ref)
+    # Householder (definition oracle) agrees as well.
+    Qh, Rh = oracle.householder_qr(Y)
+    tol = 8 * np.linalg.cond(Y) * n * EPS
+    np.testing.assert_allclose(Qg, Qh, rtol=0, atol=tol)
+    # Solve: the oracle's x from the oracle's factors, and the HPL residual.
+    xo, rc = oracle.qr_solve(ref["Q"], ref["R"], rhs)
+    assert rc == 0
+    np.testing.assert_allclose(xg, xo, rtol=0, atol=tol * np.abs(xo).max())
+    assert hpl_ratio(Y, xg, rhs) < 16
+
+
+@pytest.mark.parametrize("q,r,b", [(300, 200, 64), (129, 129, 128), (1000, 70, 32), (7, 5, 2), (40, 33, 1),
+                                   (257, 256, 128), (520, 520, 100), (64, 64, 64), (1, 1, 1), (5000, 130, 128)])
+def test_ragged_and_edge_shapes(q, r, b):
+    Y = inputs.uniform_matrix(q, r, seed=q + r + b)
+    Qg, Rg, info, flags = _factor(Y, b)
+    _compare(Y, b, Qg, Rg, info, flags)
+
+
+def test_padded_leading_dimension():
+    Y = inputs.uniform_matrix(200, 150, seed=3)
+    Qg, Rg, info, flags = _factor(Y, 64, ld=211)
+    _compare(Y, 64, Qg, Rg, info, flags)
+
+
+def test_tall_skinny_paper_shape():
+    """The orthogonalisation shape of the paper's dense experiments: q = 1e5,
+    r = 64, b = 16, Gaussian entries."""
+    Y = inputs.normal_matrix(100000, 64, seed=0)
+    Qg, Rg, info, flags = _factor(Y, 16)
+    _compare(Y, 16, Qg, Rg, info, flags)
+
+
+@pytest.mark.parametrize("n,b", [(64, 16), (200, 64), (333, 128)])
+def test_permutation_bit_exact(n, b):
+    """Permutation input: every Gram is exactly I and every projection exactly
+    0, so Q = Y and R = I with no rounding on the GPU either."""
+    Y = np.eye(n)[:, np.random.default_rng(n).permutation(n)]
+    Qg, Rg, info, flags = _factor(Y, b)
+    assert np.array_equal(Qg, Y) and np.array_equal(Rg, np.eye(n))
+    assert info == 0 and not any(flags)
+
+
+def test_power_of_two_diagonal_bit_exact():
+    d = np.array([2.0 ** ((-1) ** j * (j % 7)) * (-1) ** (j // 3) for j in range(96)])
+    Y = np.diag(d)
+    Qg, Rg, info, flags = _factor(Y, 32)
+    assert np.array_equal(Qg, np.diag(np.sign(d)))
+    assert np.array_equal(Rg, np.diag(np.abs(d)))
+
+
+def test_fallback_on_hilbert_block():
+    """A Hilbert block breaks the Cholesky factorisation; the block falls back to
+    CGS2 on both sides, with the same info and flags."""
+    w = 12
+    Y = inputs.uniform_matrix(60, 3 * w, seed=8)
+    i, j = np.arange(60), np.arange(w)
+    Y[:, w:2 * w] = 1.0 / (i[:, None] + j[None, :] + 1.0)
+    Qg, Rg, info, flags = _factor(Y, w)
+    ref = oracle.cgs_qr(Y, w)
+    assert info == ref["info"] == 2
+    assert list(flags) == list(ref["block_flags"]) == [0, 1, 0]
+    assert np.linalg.norm(Y - Qg @ Rg) < 1e-14 * np.linalg.norm(Y)
+    assert orth_ratio(Qg) < 16
+
+
+def test_zero_column_flagged():
+    Y = inputs.uniform_matrix(30, 12, seed=9)
+    Y[:, 5] = 0.0
+    Qg, Rg, info, flags = _factor(Y, 4)
+    ref = oracle.cgs_qr(Y, 4)
+    assert info == ref["info"] == 2
+    assert list(flags) == list(ref["block_flags"]) == [0, 3, 0]
+    assert Rg[5, 5] == 0.0 and not Qg[:, 5].any()
+    np.testing.assert_allclose(Qg @ Rg, Y, atol=1e-13)
+    keep = [c for c in range(12) if c != 5]
+    np.testing.assert_allclose(Qg[:, keep], ref["Q"][:, keep], atol=1e-12)
+    np.testing.assert_allclose(Rg, ref["R"], atol=1e-12)
+
+
+def test_orth_and_orth_against_match_algorithms_4_and_5():
+    Y = inputs.uniform_matrix(2000, 96, seed=4)
+    Qd, Rd, info = cqr.orth(to_dev(Y[:, :48]))
+    Qo, Ro, rc = oracle.cholqr2(Y[:, :48])
+    assert info == 0 and rc == 0
+    np.testing.assert_allclose(to_host(Qd), Qo, atol=1e-12)
+    np.testing.assert_allclose(to_host(Rd), Ro, atol=1e-12)
+    P = Qo
+    Qd2, Hd, Rd2, info2 = cqr.orth_against(to_dev(Y[:, 48:]), to_dev(P))
+    Qo2, Ho, Ro2, rc2 = oracle.cgs_cqr2(Y[:, 48:], P)
+    assert info2 == 0 and rc2 == 0
+    np.testing.assert_allclose(to_host(Qd2), Qo2, atol=1e-12)
+    np.testing.assert_allclose(to_host(Hd), Ho, atol=1e-12)
+    np.testing.assert_allclose(to_host(Rd2), Ro2, atol=1e-12)
+
+
+def test_orth_against_fallback():
+    """Algorithm 5 with a Hilbert block Q: fallback taken, contract still holds."""
+    rng = np.random.default_rng(2)
+    P, _ = np.linalg.qr(rng.standard_normal((80, 10)))
+    i, j = np.arange(80), np.arange(12)
+    Qin = 1.0 / (i[:, None] + j[None, :] + 1.0)
+    Qd, Hd, Rd, info = cqr.orth_against(to_dev(Qin), to_dev(P))
+    Qg, Hg, Rg = to_host(Qd), to_host(Hd), to_host(Rd)
+    assert info == 1
+    assert np.linalg.norm(Qin - P @ Hg - Qg @ Rg) < 1e-13 * np.linalg.norm(Qin)
+    assert np.abs(P.T @ Qg).max() < 1e-13
+    assert orth_ratio(Qg) < 16
+
+
+def test_repeated_runs_bit_identical():
+    """No atomics on the result path: two runs give identical bits."""
+    Y = inputs.uniform_matrix(3000, 300, seed=5)
+    a = _factor(Y, 64)
+    c = _factor(Y, 64)
+    assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
+
+
+def test_synth_matches_cpu_generator():
+    A = cqr.colmajor(1000, 37)
+    cqr.synth_uniform(A, seed=42, lo=-1.0, hi=1.0)
+    got = to_host(A)
+    np.testing.assert_array_equal(got, inputs.uniform_matrix(1000, 37, 42))
+    B = cqr.colmajor(64, 5)
+    cqr.synth_uniform(B, seed=7, lo=-0.5, hi=0.5)
+    np.testing.assert_array_equal(to_host(B), inputs.uniform_matrix(64, 5, 7, -0.5, 0.5))
