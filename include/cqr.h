@@ -17,6 +17,7 @@
  *   - The caller owns every buffer.  The library never allocates device
  *     memory; scratch space is the caller's `work` buffer of at least the size
  *     the matching *_workspace_size function returns (256-byte aligned).
+ *   - Leading dimensions are at most 4,000,000 (CQR_ERR_UNSUPPORTED beyond).
  *   - Return value: CQR_OK (0); -i if argument i (1-based position in the
  *     C signature) is invalid; CQR_ERR_* below otherwise.  On an argument error
  *     nothing is enqueued.

@@ -217,26 +217,49 @@ hipError_t launch_tile(int64_t M, int64_t N, int64_t K, double alpha, const doub
   return hipGetLastError();
 }
 
+// Tile shapes, largest first.  A launch wants at least kMinWG workgroups
+// (two resident per CU on 256 CUs); the largest tile that still gives that
+// many is used, else the one that gives the most.
+constexpr int kMinWG = 512;
+
+int64_t tiles_for(int64_t M, int64_t N, int mt, int nt) { return ((M + mt - 1) / mt) * ((N + nt - 1) / nt); }
+
+void pick_tile(int64_t M, int64_t N, int nsplit, int* mt, int* nt) {
+  static const int cand[4][2] = {{128, 128}, {128, 64}, {64, 128}, {64, 64}};
+  int best = 3;
+  for (int c = 0; c < 4; ++c) {
+    if ((cand[c][0] == 128 && M <= 64) || (cand[c][1] == 128 && N <= 64)) continue;
+    if (tiles_for(M, N, cand[c][0], cand[c][1]) * nsplit >= kMinWG) {
+      best = c;
+      break;
+    }
+  }
+  *mt = cand[best][0];
+  *nt = cand[best][1];
+}
+
 template <int ROLE, bool TA>
 hipError_t launch_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
                        const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int64_t kchunk, int nsplit,
                        double* part, const int* gate, hipStream_t s) {
-  const bool bigM = M > 64, bigN = N > 64;
-  if (bigM && bigN)
+  int mt, nt;
+  pick_tile(M, N, nsplit, &mt, &nt);
+  if (mt == 128 && nt == 128)
     return launch_tile<ROLE, TA, 128, 128>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, nsplit, part,
                                            gate, s);
-  if (bigM)
+  if (mt == 128)
     return launch_tile<ROLE, TA, 128, 64>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, nsplit, part, gate,
                                           s);
-  if (bigN)
+  if (nt == 128)
     return launch_tile<ROLE, TA, 64, 128>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, nsplit, part, gate,
                                           s);
   return launch_tile<ROLE, TA, 64, 64>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, nsplit, part, gate, s);
 }
 
+// Tiles of the largest shape that fits (M, N): the split-K count is chosen
+// against this before the final tile choice.
 int64_t tiles_of(int64_t M, int64_t N) {
-  const int64_t mt = M > 64 ? 128 : 64, nt = N > 64 ? 128 : 64;
-  return ((M + mt - 1) / mt) * ((N + nt - 1) / nt);
+  return tiles_for(M, N, M > 64 ? 128 : 64, N > 64 ? 128 : 64);
 }
 
 // The kernels address a thread's elements inside one tile with 32-bit byte
@@ -247,8 +270,8 @@ bool ld_ok(int64_t ld) { return ld > 0 && ld <= kMaxLd; }
 
 int choose_splits(int64_t M, int64_t N, int64_t K, size_t part_cap) {
   const int64_t tiles = tiles_of(M, N);
-  const int64_t target = 1024;
-  if (tiles >= target / 2 || K <= 4 * kKT) return 1;
+  const int64_t target = kMinWG;
+  if (tiles >= target || K <= 4 * kKT) return 1;
   int64_t splits = (target + tiles - 1) / tiles;
   const int64_t by_k = K / (4 * kKT);  // every split walks at least 4 stages
   if (splits > by_k) splits = by_k;
