@@ -105,9 +105,10 @@ struct Work {
 };
 
 size_t part_capacity(int64_t q, int64_t r, int64_t b) {
-  // Enough for ~512 splits of a b x b Gram matrix, capped at 64 MiB.
-  const size_t want = (size_t)512 * (size_t)b * (size_t)b;
-  const size_t cap = (size_t)8 << 20;
+  // Enough for the split-K partial sums of the projections (about 512
+  // workgroups of 128 x 128 tiles), capped at 256 MiB.
+  const size_t want = (size_t)512 * 128 * 128 + (size_t)4 * (size_t)r * (size_t)b;
+  const size_t cap = (size_t)32 << 20;
   size_t v = want > cap ? cap : want;
   const size_t by_size = (size_t)(q > 0 ? q : 1) * (size_t)(r > b ? r : b) * 2;
   if (v > by_size) v = by_size;

@@ -4,24 +4,38 @@
 // of steps S1/S2/S3/S6/S7/S8, the TRSMs of S5/S10 as a product with the
 // inverted triangular factor, and the small products of S11/S12).
 //
-// Tiling: a 256-thread workgroup (4 wave64s in a 2 x 2 grid) computes an
-// MT x NT tile of C; each wave owns (MT/2) x (NT/2) as 16 x 16 MFMA subtiles
-// accumulated in registers.  K is walked in KT-deep stages staged through LDS:
-// the next stage's global loads are issued into registers before the current
-// stage's MFMAs, then written to LDS behind a barrier.
+// Tiling (both kernels): a 256-thread workgroup (4 wave64s in a 2 x 2 grid)
+// computes an MT x NT tile of C; each wave owns (MT/2) x (NT/2) as 16 x 16
+// MFMA subtiles accumulated in registers, and K is walked in 16-deep stages
+// staged through LDS.
 //
-// LDS layout (both operands): element (k, x) of a KT x X stage lives at
-//   k * (X + 16) + (x ^ ((k >> 1) & 7)).
-// The row stride X + 16 puts the two 16-lane halves of each 32-lane MFMA
-// operand read in opposite halves of the 64 banks; the XOR swizzle keeps the
-// k-contiguous global->LDS writes (16 consecutive k of one column per 16
-// lanes) conflict-free as well.
+// gemm_dma_kernel (used whenever operands are 16-byte aligned with even
+// leading dimensions and K is a multiple of 16): each stage is copied
+// global -> LDS by the LDS-DMA load (global_load_lds_dwordx4, 16 bytes per
+// lane, no registers), into an S-slot ring with one barrier per stage; every
+// ring slot is a separate LDS object so the compiler can tell a stage's reads
+// from the DMA writes still in flight to the other slots.  Layouts:
+//   k-contiguous operand (A of A^T B, and B): column x holds 8 chunks of two
+//     k values; chunk c of column x sits at slot c ^ ((x >> 1) & 7), so the 16
+//     lanes of an MFMA operand read (16 columns, one k) hit 16 distinct bank
+//     groups;
+//   m-contiguous operand (A of A B): column k holds row pairs; pair c sits at
+//     position c ^ (8 ((k >> 2) & 1)), putting the two 16-lane halves of a
+//     32-lane read in opposite bank halves.
+// MFMA step kq takes k = 4 (lane / 16) + kq, so each lane's four k values are
+// one contiguous run (read as 128-bit LDS loads).
+//
+// gemm_reg_kernel (any alignment, any K): global loads into registers before
+// the current stage's MFMAs, written to LDS behind a barrier; LDS element
+// (k, x) at k (X + 16) + (x ^ ((k >> 1) & 7)).
 //
 // MFMA lane layout (measured on gfx950): lane l supplies A(l%16, l/16) and
 // B(l/16, l%16) and holds C(l/16 + 4v, l%16) in accumulator element v.  Rows
 // of A are fed through the permutation p(i) = 4 (i % 4) + i / 4, so that lane
 // l's four accumulator elements are the four consecutive rows 4 (l/16) .. +3
 // of its column, stored contiguously.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace cqr {
@@ -50,7 +64,7 @@ __device__ __forceinline__ int lds_index(int k, int x) {
 // blockIdx.x: M tile, blockIdx.y: N tile, blockIdx.z: K split of length kchunk.
 template <int ROLE, bool TA, int MT, int NT, int KT>
 __global__ void __launch_bounds__(kThreads, CQR_GEMM_OCC)
-gemm_f64_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A, int64_t lda,
+gemm_reg_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A, int64_t lda,
                 const double* __restrict__ B, int64_t ldb, double beta, double* C, int64_t ldc, int64_t kchunk,
                 double* __restrict__ part, const int* __restrict__ gate) {
   if (gate != nullptr && *gate != 0) return;
@@ -187,6 +201,191 @@ gemm_f64_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __r
     }
 }
 
+
+// ------------------------------------------------------------------------
+// LDS-DMA kernel.
+// ------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) void lds_void;
+constexpr int kDmaKT = 16;
+
+// 16-byte global -> LDS copy per lane; lane l lands at lds_base + 16 l.
+__device__ __forceinline__ void dma16(const double* g, double* lds_base) {
+  __builtin_amdgcn_global_load_lds((const void*)g, (lds_void*)lds_base, 16, 0, 0);
+}
+
+// Wait until at most N vector-memory operations of this wave are outstanding.
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// Element (k, x) of a k-contiguous stage (X columns of 16 k values).
+__device__ __forceinline__ int kc_index(int k, int x) { return x * 16 + 2 * ((k >> 1) ^ ((x >> 1) & 7)) + (k & 1); }
+// Element (m, k) of an m-contiguous stage (16 columns of X rows).
+template <int X>
+__device__ __forceinline__ int mc_index(int m, int k) {
+  return k * X + 2 * ((m >> 1) ^ (8 * ((k >> 2) & 1))) + (m & 1);
+}
+
+// Same contract as gemm_reg_kernel; requires K and kchunk multiples of 16,
+// 16-byte aligned A and B, even lda and ldb, and (for !TA) even M.
+template <int ROLE, bool TA, int MT, int NT, int S, int OCC>
+__global__ void __launch_bounds__(kThreads, OCC)
+gemm_dma_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A, int64_t lda,
+                const double* __restrict__ B, int64_t ldb, double beta, double* C, int64_t ldc, int64_t kchunk,
+                double* __restrict__ part, const int* __restrict__ gate) {
+  static_assert(S == 2 || S == 3, "ring depth");
+  if (gate != nullptr && *gate != 0) return;
+  constexpr int KT = kDmaKT;
+  constexpr int WM = 2, WN = 2;
+  constexpr int WTM = MT / WM, WTN = NT / WN;
+  constexpr int SM = WTM / 16, SN = WTN / 16;
+  constexpr int ASTAGE = MT * KT, BSTAGE = NT * KT;                 // doubles per stage
+  constexpr int AINS = ASTAGE / 128 / 4, BINS = BSTAGE / 128 / 4;   // DMA instructions per wave per stage
+  static_assert(AINS >= 1 && BINS >= 1 && SM >= 1 && SN >= 1, "tile shape");
+  __shared__ __attribute__((aligned(16))) double sA0[ASTAGE], sA1[ASTAGE], sA2[S > 2 ? ASTAGE : 2];
+  __shared__ __attribute__((aligned(16))) double sB0[BSTAGE], sB1[BSTAGE], sB2[S > 2 ? BSTAGE : 2];
+  auto slotA = [&](auto c) -> double* {
+    if constexpr (c.value == 0) return sA0;
+    else if constexpr (c.value == 1) return sA1;
+    else return sA2;
+  };
+  auto slotB = [&](auto c) -> double* {
+    if constexpr (c.value == 0) return sB0;
+    else if constexpr (c.value == 1) return sB1;
+    else return sB2;
+  };
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave % WM, wn = wave / WM;
+  const int li = lane & 15, lg = lane >> 4;
+  const int prow = 4 * (li & 3) + (li >> 2);
+  const int64_t m0 = (int64_t)blockIdx.x * MT;
+  const int64_t n0 = (int64_t)blockIdx.y * NT;
+  const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+  const int64_t kend = (K < kbeg + kchunk) ? K : kbeg + kchunk;
+  const int nst = (kend > kbeg) ? (int)((kend - kbeg) / KT) : 0;
+
+  // Source offsets (elements from the stage origin) of this lane's chunks.
+  // Columns past the matrix are clamped to the last one; their values only
+  // reach output rows/columns that are never stored.
+  int64_t aoff[AINS], boff[BINS];
+#pragma unroll
+  for (int t = 0; t < AINS; ++t) {
+    const int p = (wave * AINS + t) * 64 + lane;  // chunk position in the stage
+    if (TA) {
+      const int x = p / 8, c = (p % 8) ^ ((x >> 1) & 7);
+      const int64_t m = (m0 + x < M) ? m0 + x : M - 1;
+      aoff[t] = 2 * c + m * lda;
+    } else {
+      constexpr int CPC = MT / 2;  // row pairs per column
+      const int kk = p / CPC, c = (p % CPC) ^ (8 * ((kk >> 2) & 1));
+      const int64_t m = (m0 + 2 * c < M) ? m0 + 2 * c : M - 2;
+      aoff[t] = m + (int64_t)kk * lda;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < BINS; ++t) {
+    const int p = (wave * BINS + t) * 64 + lane;
+    const int x = p / 8, c = (p % 8) ^ ((x >> 1) & 7);
+    const int64_t n = (n0 + x < N) ? n0 + x : N - 1;
+    boff[t] = 2 * c + n * ldb;
+  }
+
+  auto issue = [&](int st, auto slot) {
+    const int64_t k0 = kbeg + (int64_t)st * KT;
+    const double* ga = A + (TA ? k0 : k0 * lda);
+    const double* gb = B + k0;
+    double* la = slotA(slot);
+    double* lb = slotB(slot);
+#pragma unroll
+    for (int t = 0; t < AINS; ++t) dma16(ga + aoff[t], la + (wave * AINS + t) * 128);
+#pragma unroll
+    for (int t = 0; t < BINS; ++t) dma16(gb + boff[t], lb + (wave * BINS + t) * 128);
+  };
+
+  d4 acc[SM][SN];
+#pragma unroll
+  for (int i = 0; i < SM; ++i)
+#pragma unroll
+    for (int j = 0; j < SN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  auto compute = [&](auto slot) {
+    const double* cA = slotA(slot);
+    const double* cB = slotB(slot);
+#pragma unroll
+    for (int kq = 0; kq < 4; ++kq) {
+      const int k = 4 * lg + kq;
+      double af[SM], bf[SN];
+#pragma unroll
+      for (int i = 0; i < SM; ++i) {
+        const int m = wm * WTM + i * 16 + prow;
+        af[i] = TA ? cA[kc_index(k, m)] : cA[mc_index<MT>(m, k)];
+      }
+#pragma unroll
+      for (int j = 0; j < SN; ++j) bf[j] = cB[kc_index(k, wn * WTN + j * 16 + li)];
+#pragma unroll
+      for (int i = 0; i < SM; ++i)
+#pragma unroll
+        for (int j = 0; j < SN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+  };
+
+  constexpr int PER_STAGE = AINS + BINS;  // DMA operations per wave per stage
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  // Stage st lives in slot st % S.  Its DMA is complete once at most S - 2
+  // later stages are outstanding; the barrier then also guarantees that every
+  // wave has finished reading the slot the next DMA overwrites.
+  auto step = [&](int st, auto cur, auto nxt) {
+    if (st + S - 2 < nst) wait_vmcnt<(S - 2) * PER_STAGE>();
+    else wait_vmcnt<0>();
+    __syncthreads();
+    if (st + S - 1 < nst) issue(st + S - 1, nxt);
+    compute(cur);
+  };
+  if (nst > 0) issue(0, I0{});
+  if (S > 2 && nst > 1) issue(1, I1{});
+  for (int st = 0; st < nst; st += S) {
+    if constexpr (S == 2) {
+      step(st, I0{}, I1{});
+      if (st + 1 < nst) step(st + 1, I1{}, I0{});
+    } else {
+      step(st, I0{}, I2{});
+      if (st + 1 < nst) step(st + 1, I1{}, I0{});
+      if (st + 2 < nst) step(st + 2, I2{}, I1{});
+    }
+  }
+
+  const int64_t zoff = (int64_t)blockIdx.z * M * N;
+#pragma unroll
+  for (int i = 0; i < SM; ++i)
+#pragma unroll
+    for (int j = 0; j < SN; ++j) {
+      const int64_t n = n0 + wn * WTN + j * 16 + li;
+      const int64_t mb = m0 + wm * WTM + i * 16 + 4 * lg;
+      if (n >= N) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t m = mb + v;
+        if (m >= M) continue;
+        const double val = acc[i][j][v];
+        if (part != nullptr) {
+          part[zoff + m + n * M] = val;
+        } else {
+          double c = alpha * val;
+          if (beta != 0.0) c += beta * C[m + n * ldc];
+          C[m + n * ldc] = c;
+        }
+      }
+    }
+}
+
 // C = alpha * sum_z part[z] + beta * C, summed in split order (deterministic).
 __global__ void __launch_bounds__(256)
 splitk_reduce_kernel(int64_t M, int64_t N, int nsplit, const double* __restrict__ part, double alpha, double beta,
@@ -207,110 +406,145 @@ splitk_reduce_kernel(int64_t M, int64_t N, int nsplit, const double* __restrict_
 constexpr int kKT = CQR_GEMM_KT;
 constexpr int64_t kMaxLd = 4000000;
 
-template <int ROLE, bool TA, int MT, int NT>
-hipError_t launch_tile(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
-                       const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int64_t kchunk, int nsplit,
-                       double* part, const int* gate, hipStream_t s) {
-  const dim3 grid((unsigned)((M + MT - 1) / MT), (unsigned)((N + NT - 1) / NT), (unsigned)nsplit);
-  hipLaunchKernelGGL((gemm_f64_kernel<ROLE, TA, MT, NT, kKT>), grid, dim3(kThreads), 0, s, M, N, K, alpha, A,
-                     lda, B, ldb, beta, C, ldc, kchunk, part, gate);
-  return hipGetLastError();
-}
-
-// Tile shapes, largest first.  A launch wants at least kMinWG workgroups
-// (two resident per CU on 256 CUs); the largest tile that still gives that
-// many is used, else the one that gives the most.
-constexpr int kMinWG = 512;
+// The register kernel addresses a thread's elements inside one tile with
+// 32-bit byte offsets: 8 * (KT + 128 * ld) must stay below 2^32.
+bool ld_ok(int64_t ld) { return ld > 0 && ld <= kMaxLd; }
 
 int64_t tiles_for(int64_t M, int64_t N, int mt, int nt) { return ((M + mt - 1) / mt) * ((N + nt - 1) / nt); }
 
-void pick_tile(int64_t M, int64_t N, int nsplit, int* mt, int* nt) {
-  static const int cand[4][2] = {{128, 128}, {128, 64}, {64, 128}, {64, 64}};
-  int best = 3;
-  for (int c = 0; c < 4; ++c) {
-    if ((cand[c][0] == 128 && M <= 64) || (cand[c][1] == 128 && N <= 64)) continue;
-    if (tiles_for(M, N, cand[c][0], cand[c][1]) * nsplit >= kMinWG) {
-      best = c;
-      break;
+struct Plan {
+  bool dma;
+  int mt, nt;
+  int nsplit;
+  int64_t kchunk;
+};
+
+bool dma_eligible(bool ta, int64_t M, int64_t K, const double* A, int64_t lda, const double* B, int64_t ldb) {
+  if ((reinterpret_cast<uintptr_t>(A) & 15) || (reinterpret_cast<uintptr_t>(B) & 15)) return false;
+  if ((lda & 1) || (ldb & 1)) return false;
+  if (K % kDmaKT != 0) return false;
+  if (!ta && ((M & 1) || M < 2)) return false;
+  return true;
+}
+
+// Tile shape: the largest that still occupies every CU (one 128 x 128
+// workgroup per CU, two of the 64-wide shapes), else the smallest.
+void pick_tile(bool ta, int64_t M, int64_t N, int nsplit, int* mt, int* nt) {
+  const bool bigM = M > 64, bigN = N > 64;
+  if (bigM && bigN) {
+    const int64_t need = ta ? 512 : 256;
+    if (tiles_for(M, N, 128, 128) * nsplit >= need) { *mt = 128; *nt = 128; return; }
+    if (ta) { *mt = 128; *nt = 128; return; }
+    *mt = 64; *nt = 128;
+    return;
+  }
+  *mt = bigM ? 128 : 64;
+  *nt = bigN ? 128 : 64;
+}
+
+Plan plan_gemm(bool ta, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B, int64_t ldb,
+               bool allow_split, size_t part_cap) {
+  Plan p;
+  p.dma = dma_eligible(ta, M, K, A, lda, B, ldb);
+  const int kt = p.dma ? kDmaKT : kKT;
+  p.nsplit = 1;
+  if (allow_split && ta) {
+    // Split the reduction so that about 512 workgroups run, each walking at
+    // least 8 stages, within the partial-sum buffer.
+    const int64_t tiles = tiles_for(M, N, M > 64 ? 128 : 64, N > 64 ? 128 : 64);
+    if (tiles < 512) {
+      int64_t splits = (512 + tiles - 1) / tiles;
+      const int64_t by_k = K / (8 * kt);
+      if (splits > by_k) splits = by_k;
+      const int64_t by_cap = (int64_t)(part_cap / (size_t)(M * N));
+      if (splits > by_cap) splits = by_cap;
+      p.nsplit = splits < 1 ? 1 : (int)splits;
     }
   }
-  *mt = cand[best][0];
-  *nt = cand[best][1];
+  p.kchunk = K > 0 ? K : 1;
+  if (p.nsplit > 1) {
+    p.kchunk = (K + p.nsplit - 1) / p.nsplit;
+    p.kchunk = (p.kchunk + kt - 1) / kt * kt;
+    p.nsplit = (int)((K + p.kchunk - 1) / p.kchunk);
+  }
+  if (p.dma) {
+    pick_tile(ta, M, N, p.nsplit, &p.mt, &p.nt);
+  } else {
+    p.mt = M > 64 ? 128 : 64;
+    p.nt = N > 64 ? 128 : 64;
+    if (p.mt == 128 && p.nt == 128 && tiles_for(M, N, 128, 128) * p.nsplit < 512) p.mt = 64;
+  }
+  return p;
 }
 
+template <int ROLE, bool TA, int MT, int NT, int S, int OCC>
+hipError_t launch_dma(const Plan& p, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+                      const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double* part, const int* gate,
+                      hipStream_t s) {
+  const dim3 grid((unsigned)((M + MT - 1) / MT), (unsigned)((N + NT - 1) / NT), (unsigned)p.nsplit);
+  hipLaunchKernelGGL((gemm_dma_kernel<ROLE, TA, MT, NT, S, OCC>), grid, dim3(kThreads), 0, s, M, N, K, alpha, A,
+                     lda, B, ldb, beta, C, ldc, p.kchunk, part, gate);
+  return hipGetLastError();
+}
+
+template <int ROLE, bool TA, int MT, int NT>
+hipError_t launch_reg(const Plan& p, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+                      const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double* part, const int* gate,
+                      hipStream_t s) {
+  const dim3 grid((unsigned)((M + MT - 1) / MT), (unsigned)((N + NT - 1) / NT), (unsigned)p.nsplit);
+  hipLaunchKernelGGL((gemm_reg_kernel<ROLE, TA, MT, NT, kKT>), grid, dim3(kThreads), 0, s, M, N, K, alpha, A, lda,
+                     B, ldb, beta, C, ldc, p.kchunk, part, gate);
+  return hipGetLastError();
+}
+
+// Ring depth / occupancy per DMA tile: 128x128 A^T B uses 2 slots at two
+// workgroups per CU; 128x128 A B uses 3 slots at one workgroup per CU; the
+// smaller shapes use 3 slots.
 template <int ROLE, bool TA>
-hipError_t launch_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
-                       const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int64_t kchunk, int nsplit,
-                       double* part, const int* gate, hipStream_t s) {
-  int mt, nt;
-  pick_tile(M, N, nsplit, &mt, &nt);
-  if (mt == 128 && nt == 128)
-    return launch_tile<ROLE, TA, 128, 128>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, nsplit, part,
-                                           gate, s);
-  if (mt == 128)
-    return launch_tile<ROLE, TA, 128, 64>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, nsplit, part, gate,
-                                          s);
-  if (nt == 128)
-    return launch_tile<ROLE, TA, 64, 128>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, nsplit, part, gate,
-                                          s);
-  return launch_tile<ROLE, TA, 64, 64>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, nsplit, part, gate, s);
+hipError_t launch(const Plan& p, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+                  const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double* part, const int* gate,
+                  hipStream_t s) {
+  if (p.dma) {
+    if (p.mt == 128 && p.nt == 128) {
+      if (TA) return launch_dma<ROLE, TA, 128, 128, 2, 2>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
+      return launch_dma<ROLE, TA, 128, 128, 3, 1>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
+    }
+    if (p.mt == 128) return launch_dma<ROLE, TA, 128, 64, 3, 2>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
+    if (p.nt == 128) return launch_dma<ROLE, TA, 64, 128, 3, 2>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
+    return launch_dma<ROLE, TA, 64, 64, 3, 3>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
+  }
+  if (p.mt == 128 && p.nt == 128) return launch_reg<ROLE, TA, 128, 128>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
+  if (p.mt == 128) return launch_reg<ROLE, TA, 128, 64>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
+  if (p.nt == 128) return launch_reg<ROLE, TA, 64, 128>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
+  return launch_reg<ROLE, TA, 64, 64>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
 }
-
-// Tiles of the largest shape that fits (M, N): the split-K count is chosen
-// against this before the final tile choice.
-int64_t tiles_of(int64_t M, int64_t N) {
-  return tiles_for(M, N, M > 64 ? 128 : 64, N > 64 ? 128 : 64);
-}
-
-// The kernels address a thread's elements inside one tile with 32-bit byte
-// offsets: 8 * (KT + 128 * ld) must stay below 2^32.
-bool ld_ok(int64_t ld) { return ld > 0 && ld <= kMaxLd; }
 
 }  // namespace
-
-int choose_splits(int64_t M, int64_t N, int64_t K, size_t part_cap) {
-  const int64_t tiles = tiles_of(M, N);
-  const int64_t target = kMinWG;
-  if (tiles >= target || K <= 4 * kKT) return 1;
-  int64_t splits = (target + tiles - 1) / tiles;
-  const int64_t by_k = K / (4 * kKT);  // every split walks at least 4 stages
-  if (splits > by_k) splits = by_k;
-  const int64_t by_cap = (int64_t)(part_cap / (size_t)(M * N));
-  if (splits > by_cap) splits = by_cap;
-  return splits < 1 ? 1 : (int)splits;
-}
 
 hipError_t gemm_tn(Role role, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
                    const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double* part, size_t part_cap,
                    const int* gate, hipStream_t s, double flops) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (!ld_ok(lda) || !ld_ok(ldb)) return hipErrorInvalidValue;
-  int nsplit = (part != nullptr) ? choose_splits(M, N, K, part_cap) : 1;
-  int64_t kchunk = K;
-  if (nsplit > 1) {
-    kchunk = (K + nsplit - 1) / nsplit;
-    kchunk = (kchunk + kKT - 1) / kKT * kKT;
-    nsplit = (int)((K + kchunk - 1) / kchunk);
-  }
-  if (kchunk < 1) kchunk = 1;
+  const Plan p = plan_gemm(true, M, N, K, A, lda, B, ldb, part != nullptr, part_cap);
   const double bytes = 8.0 * ((double)K * M + (double)K * N + (double)M * N * (beta != 0.0 ? 2.0 : 1.0));
+  double* pp = p.nsplit > 1 ? part : nullptr;
   const int slot = prof_begin(s);
   hipError_t e;
-  double* p = nsplit > 1 ? part : nullptr;
   if (role == ROLE_GRAM)
-    e = launch_gemm<ROLE_GRAM, true>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, nsplit, p, gate, s);
+    e = launch<ROLE_GRAM, true>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, pp, gate, s);
   else
-    e = launch_gemm<ROLE_PROJ, true>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, nsplit, p, gate, s);
+    e = launch<ROLE_PROJ, true>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, pp, gate, s);
   prof_end(slot, role, s, flops, bytes);
-  if (e != hipSuccess || nsplit == 1) return e;
+  if (e != hipSuccess || p.nsplit == 1) return e;
   const int64_t total = M * N;
   int64_t blocks = (total + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   const int slot2 = prof_begin(s);
-  hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, M, N, nsplit, part, alpha, beta,
-                     C, ldc, gate);
+  hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, M, N, p.nsplit, part, alpha,
+                     beta, C, ldc, gate);
   e = hipGetLastError();
-  prof_end(slot2, ROLE_REDUCE, s, 0.0, 8.0 * (double)total * (nsplit + (beta != 0.0 ? 2 : 1)));
+  prof_end(slot2, ROLE_REDUCE, s, 0.0, 8.0 * (double)total * (p.nsplit + (beta != 0.0 ? 2 : 1)));
   return e;
 }
 
@@ -319,19 +553,19 @@ hipError_t gemm_nn(Role role, int64_t M, int64_t N, int64_t K, double alpha, con
                    double flops) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (!ld_ok(lda) || !ld_ok(ldb)) return hipErrorInvalidValue;
+  const Plan p = plan_gemm(false, M, N, K, A, lda, B, ldb, false, 0);
   const double bytes = 8.0 * ((double)K * M + (double)K * N + (double)M * N * (beta != 0.0 ? 2.0 : 1.0));
-  const int64_t kchunk = K > 0 ? K : 1;
   const int slot = prof_begin(s);
   hipError_t e;
   switch (role) {
     case ROLE_UPDATE:
-      e = launch_gemm<ROLE_UPDATE, false>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, 1, nullptr, gate, s);
+      e = launch<ROLE_UPDATE, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, gate, s);
       break;
     case ROLE_TRSM:
-      e = launch_gemm<ROLE_TRSM, false>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, 1, nullptr, gate, s);
+      e = launch<ROLE_TRSM, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, gate, s);
       break;
     default:
-      e = launch_gemm<ROLE_SMALL, false>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, 1, nullptr, gate, s);
+      e = launch<ROLE_SMALL, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, gate, s);
       break;
   }
   prof_end(slot, role, s, flops, bytes);

@@ -31,11 +31,6 @@ const char* role_name(int role);
 int prof_begin(hipStream_t s);
 void prof_end(int slot, int role, hipStream_t s, double flops, double bytes);
 
-// Split-K partial-sum buffer capacity chooser: returns the number of K splits
-// for a TN GEMM of M x N output and reduction length K, given the capacity of
-// the partial buffer in doubles.
-int choose_splits(int64_t M, int64_t N, int64_t K, size_t part_cap);
-
 // C = alpha * A^T B + beta * C;  A: K x M (lda), B: K x N (ldb), C: M x N (ldc).
 // Split over K through `part` (capacity part_cap doubles) when it pays.
 hipError_t gemm_tn(Role role, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
