@@ -3,11 +3,16 @@
 // copies, and the two kernels of the triangular solve.
 #include "internal.h"
 
+// Thread-grid side of the Cholesky workgroup (16: 256 threads, 32: 1024).
+#ifndef CQR_CHOL_TG
+#define CQR_CHOL_TG 32
+#endif
+
 namespace cqr {
 namespace {
 
-// One 1024-thread workgroup factors W (b x b, b <= 32*TS) as L L^T and inverts L.
-// Thread (ty, tx) = (tid / 32, tid % 32) keeps the TS x TS register tile of
+// One workgroup of TG x TG threads factors W (b x b, b <= TG*TS) as L L^T and
+// inverts L.  Thread (ty, tx) = (tid / TG, tid % TG) keeps the TS x TS register tile of
 // rows ty*TS.. and columns tx*TS.. of W (then L) and of X = L^{-1}.
 //
 // Factorisation, right-looking, one barrier per column k: the owners of
@@ -18,15 +23,15 @@ namespace {
 // Inversion, right-looking on X = I, one barrier per k: row k of X is scaled
 // by 1/L(k,k) and L(i,k) times it is subtracted from every row i > k.
 // Columns/rows are double-buffered in LDS by the parity of k.
-template <int TS>
-__global__ void __launch_bounds__(1024)
+template <int TG, int TS>
+__global__ void __launch_bounds__(TG * TG)
 chol_inv_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __restrict__ LT, double* __restrict__ XT,
                 int* status, int code, int blk) {
   if (status[0] != 0) return;
-  __shared__ double colbuf[2][32 * TS];
-  __shared__ double rowbuf[2][32 * TS];
+  __shared__ double colbuf[2][TG * TS];
+  __shared__ double rowbuf[2][TG * TS];
   __shared__ int bad;
-  const int tid = threadIdx.x, ty = tid >> 5, tx = tid & 31;
+  const int tid = threadIdx.x, ty = tid / TG, tx = tid % TG;
   if (tid == 0) bad = 0;
   double w[TS][TS], x[TS][TS];
 #pragma unroll
@@ -39,7 +44,7 @@ chol_inv_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __rest
     }
   __syncthreads();
 
-  for (int kb = 0; kb < 32 && kb * TS < b; ++kb) {
+  for (int kb = 0; kb < TG && kb * TS < b; ++kb) {
 #pragma unroll
     for (int kk = 0; kk < TS; ++kk) {
       const int k = kb * TS + kk;
@@ -77,7 +82,7 @@ chol_inv_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __rest
   }
   __syncthreads();
 
-  for (int kb = 0; kb < 32 && kb * TS < b; ++kb) {
+  for (int kb = 0; kb < TG && kb * TS < b; ++kb) {
 #pragma unroll
     for (int kk = 0; kk < TS; ++kk) {
       const int k = kb * TS + kk;
@@ -214,12 +219,18 @@ hipError_t chol_inv(int b, const double* W, int64_t ldw, double* LT, double* XT,
   if (b < 1 || b > 128) return hipErrorInvalidValue;
   const double bb = (double)b;
   const int slot = prof_begin(s);
-  if (b <= 32)
-    hipLaunchKernelGGL(chol_inv_kernel<1>, dim3(1), dim3(1024), 0, s, b, W, ldw, LT, XT, status, code, blk);
+  if (b <= 16)
+    hipLaunchKernelGGL((chol_inv_kernel<CQR_CHOL_TG, 1>), dim3(1), dim3(CQR_CHOL_TG * CQR_CHOL_TG), 0, s, b, W, ldw,
+                       LT, XT, status, code, blk);
+  else if (b <= 32)
+    hipLaunchKernelGGL((chol_inv_kernel<CQR_CHOL_TG, 32 / CQR_CHOL_TG>), dim3(1), dim3(CQR_CHOL_TG * CQR_CHOL_TG), 0, s,
+                       b, W, ldw, LT, XT, status, code, blk);
   else if (b <= 64)
-    hipLaunchKernelGGL(chol_inv_kernel<2>, dim3(1), dim3(1024), 0, s, b, W, ldw, LT, XT, status, code, blk);
+    hipLaunchKernelGGL((chol_inv_kernel<CQR_CHOL_TG, 64 / CQR_CHOL_TG>), dim3(1), dim3(CQR_CHOL_TG * CQR_CHOL_TG), 0, s,
+                       b, W, ldw, LT, XT, status, code, blk);
   else
-    hipLaunchKernelGGL(chol_inv_kernel<4>, dim3(1), dim3(1024), 0, s, b, W, ldw, LT, XT, status, code, blk);
+    hipLaunchKernelGGL((chol_inv_kernel<CQR_CHOL_TG, 128 / CQR_CHOL_TG>), dim3(1), dim3(CQR_CHOL_TG * CQR_CHOL_TG), 0,
+                       s, b, W, ldw, LT, XT, status, code, blk);
   hipError_t e = hipGetLastError();
   prof_end(slot, ROLE_CHOL, s, bb * bb * bb / 3.0, 8.0 * 3.0 * bb * bb);
   return e;

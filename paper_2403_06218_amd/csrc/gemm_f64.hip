@@ -449,16 +449,24 @@ Plan plan_gemm(bool ta, int64_t M, int64_t N, int64_t K, const double* A, int64_
   const int kt = p.dma ? kDmaKT : kKT;
   p.nsplit = 1;
   if (allow_split && ta) {
-    // Split the reduction so that about 512 workgroups run, each walking at
-    // least 8 stages, within the partial-sum buffer.
+    // Split the reduction so that the workgroups fill whole rounds of the
+    // 512 resident slots (two per CU) as closely as possible, each split
+    // walking at least 8 stages and fitting the partial-sum buffer; among
+    // equally full choices the fewest splits win (less reduction traffic).
     const int64_t tiles = tiles_for(M, N, M > 64 ? 128 : 64, N > 64 ? 128 : 64);
-    if (tiles < 512) {
-      int64_t splits = (512 + tiles - 1) / tiles;
-      const int64_t by_k = K / (8 * kt);
-      if (splits > by_k) splits = by_k;
-      const int64_t by_cap = (int64_t)(part_cap / (size_t)(M * N));
-      if (splits > by_cap) splits = by_cap;
-      p.nsplit = splits < 1 ? 1 : (int)splits;
+    int64_t max_split = K / (8 * kt);
+    const int64_t by_cap = (int64_t)(part_cap / (size_t)(M * N));
+    if (max_split > by_cap) max_split = by_cap;
+    if (max_split > 64) max_split = 64;
+    double best_eff = 0.0;
+    for (int64_t sp = 1; sp <= (max_split < 1 ? 1 : max_split); ++sp) {
+      const int64_t wgs = tiles * sp;
+      const int64_t rounds = (wgs + 511) / 512;
+      const double eff = (double)wgs / (double)(rounds * 512);
+      if (eff > best_eff + 0.02) {
+        best_eff = eff;
+        p.nsplit = (int)sp;
+      }
     }
   }
   p.kchunk = K > 0 ? K : 1;
