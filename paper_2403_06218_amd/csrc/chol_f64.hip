@@ -3,44 +3,41 @@
 // copies, and the two kernels of the triangular solve.
 #include "internal.h"
 
-// Thread-grid side of the Cholesky workgroup (16: 256 threads, 32: 1024).
-#ifndef CQR_CHOL_TG
-#define CQR_CHOL_TG 32
-#endif
-
 namespace cqr {
 namespace {
 
-// One workgroup of TG x TG threads factors W (b x b, b <= TG*TS) as L L^T and
-// inverts L.  Thread (ty, tx) = (tid / TG, tid % TG) keeps the TS x TS register tile of
-// rows ty*TS.. and columns tx*TS.. of W (then L) and of X = L^{-1}.
+// One workgroup of 16 x 16 threads (4 waves, one per SIMD) factors W (b x b,
+// b <= 16 TS) as L L^T and inverts L.  Thread (ty, tx) = (tid / 16, tid % 16)
+// keeps the TS x TS register tile of rows ty*TS.. and columns tx*TS.. .
 //
 // Factorisation, right-looking, one barrier per column k: the owners of
 // column k publish its current values; every thread then takes the pivot
 // d = W(k,k), forms l = sqrt(d), scales the column by 1/l and applies the
 // rank-1 update to its tile.  A pivot that is not > 0 (NaN included) marks a
 // breakdown; the kernel still runs to the end and reports it in status.
-// Inversion, right-looking on X = I, one barrier per k: row k of X is scaled
-// by 1/L(k,k) and L(i,k) times it is subtracted from every row i > k.
-// Columns/rows are double-buffered in LDS by the parity of k.
-template <int TG, int TS>
-__global__ void __launch_bounds__(TG * TG)
+// L is then parked in LDS and the same registers hold X = L^{-1}, built
+// right-looking from X = I with one barrier per k: row k of X is scaled by
+// 1/L(k,k) and L(i,k) times it is subtracted from every row i > k.
+// Published columns/rows are double-buffered in LDS by the parity of k.
+template <int TS>
+__global__ void __launch_bounds__(256)
 chol_inv_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __restrict__ LT, double* __restrict__ XT,
                 int* status, int code, int blk) {
+  constexpr int TG = 16, NB = TG * TS;
   if (status[0] != 0) return;
-  __shared__ double colbuf[2][TG * TS];
-  __shared__ double rowbuf[2][TG * TS];
+  __shared__ double colbuf[2][NB];
+  __shared__ double rowbuf[2][NB];
+  __shared__ double sL[NB][NB + 1];
   __shared__ int bad;
   const int tid = threadIdx.x, ty = tid / TG, tx = tid % TG;
   if (tid == 0) bad = 0;
-  double w[TS][TS], x[TS][TS];
+  double w[TS][TS];
 #pragma unroll
   for (int r = 0; r < TS; ++r)
 #pragma unroll
     for (int c = 0; c < TS; ++c) {
       const int i = ty * TS + r, j = tx * TS + c;
       w[r][c] = (i < b && j < b) ? W[i + (int64_t)j * ldw] : (i == j ? 1.0 : 0.0);
-      x[r][c] = (i == j) ? 1.0 : 0.0;
     }
   __syncthreads();
 
@@ -58,28 +55,41 @@ chol_inv_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __rest
       if (tid == 0 && k < b && !(d > 0.0)) bad = 1;
       const double l = sqrt(d);
       const double rl = 1.0 / l;
-      double li[TS], lj[TS];
+      // Column entries of rows/columns <= k enter the update as exact zeros,
+      // which leaves those tile entries unchanged without per-element branches.
+      double lim[TS], ljm[TS];
 #pragma unroll
-      for (int r = 0; r < TS; ++r) li[r] = colbuf[buf][ty * TS + r] * rl;
+      for (int r = 0; r < TS; ++r) lim[r] = (ty * TS + r > k) ? colbuf[buf][ty * TS + r] * rl : 0.0;
 #pragma unroll
-      for (int c = 0; c < TS; ++c) lj[c] = colbuf[buf][tx * TS + c] * rl;
+      for (int c = 0; c < TS; ++c) ljm[c] = (tx * TS + c > k) ? colbuf[buf][tx * TS + c] * rl : 0.0;
 #pragma unroll
       for (int r = 0; r < TS; ++r)
 #pragma unroll
-        for (int c = 0; c < TS; ++c) {
-          const int i = ty * TS + r, j = tx * TS + c;
-          if (i > k && j > k) w[r][c] -= li[r] * lj[c];
-        }
+        for (int c = 0; c < TS; ++c) w[r][c] -= lim[r] * ljm[c];
       if (tx == kb) {
 #pragma unroll
         for (int r = 0; r < TS; ++r) {
           const int i = ty * TS + r;
-          if (i > k) w[r][kk] = li[r];
-          else if (i == k) w[r][kk] = l;
+          w[r][kk] = (i > k) ? lim[r] : ((i == k) ? l : w[r][kk]);
         }
       }
     }
   }
+  // Park L (lower part; zero above) in LDS and write L^T out.
+#pragma unroll
+  for (int r = 0; r < TS; ++r)
+#pragma unroll
+    for (int c = 0; c < TS; ++c) {
+      const int i = ty * TS + r, j = tx * TS + c;
+      const double v = (i >= j) ? w[r][c] : 0.0;
+      sL[i][j] = v;
+      if (i < b && j < b) LT[j + (int64_t)i * b] = v;  // LT(j, i) = L(i, j)
+    }
+  // The same registers now hold X, starting from I.
+#pragma unroll
+  for (int r = 0; r < TS; ++r)
+#pragma unroll
+    for (int c = 0; c < TS; ++c) w[r][c] = (ty * TS + r == tx * TS + c) ? 1.0 : 0.0;
   __syncthreads();
 
   for (int kb = 0; kb < TG && kb * TS < b; ++kb) {
@@ -87,28 +97,25 @@ chol_inv_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __rest
     for (int kk = 0; kk < TS; ++kk) {
       const int k = kb * TS + kk;
       const int buf = k & 1;
-      if (tx == kb) {
-#pragma unroll
-        for (int r = 0; r < TS; ++r) colbuf[buf][ty * TS + r] = w[r][kk];
-      }
       if (ty == kb) {
 #pragma unroll
-        for (int c = 0; c < TS; ++c) rowbuf[buf][tx * TS + c] = x[kk][c];
+        for (int c = 0; c < TS; ++c) rowbuf[buf][tx * TS + c] = w[kk][c];
       }
       __syncthreads();
-      const double rl = 1.0 / colbuf[buf][k];
+      const double rl = 1.0 / sL[k][k];
       double xk[TS];
 #pragma unroll
       for (int c = 0; c < TS; ++c) xk[c] = rowbuf[buf][tx * TS + c] * rl;
 #pragma unroll
       for (int r = 0; r < TS; ++r) {
         const int i = ty * TS + r;
-        const double lik = colbuf[buf][i];
+        const double lik = (i > k) ? sL[i][k] : 0.0;
 #pragma unroll
-        for (int c = 0; c < TS; ++c) {
-          if (i > k) x[r][c] -= lik * xk[c];
-          else if (i == k) x[r][c] = xk[c];
-        }
+        for (int c = 0; c < TS; ++c) w[r][c] -= lik * xk[c];
+      }
+      if (ty == kb) {
+#pragma unroll
+        for (int c = 0; c < TS; ++c) w[kk][c] = xk[c];
       }
     }
   }
@@ -118,10 +125,7 @@ chol_inv_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __rest
 #pragma unroll
     for (int c = 0; c < TS; ++c) {
       const int i = ty * TS + r, j = tx * TS + c;
-      if (i < b && j < b) {
-        LT[j + (int64_t)i * b] = (i >= j) ? w[r][c] : 0.0;  // LT(j, i) = L(i, j)
-        XT[j + (int64_t)i * b] = (i >= j) ? x[r][c] : 0.0;  // XT(j, i) = X(i, j)
-      }
+      if (i < b && j < b) XT[j + (int64_t)i * b] = (i >= j) ? w[r][c] : 0.0;  // XT(j, i) = X(i, j)
     }
   __syncthreads();
   if (tid == 0 && bad) {
@@ -220,17 +224,13 @@ hipError_t chol_inv(int b, const double* W, int64_t ldw, double* LT, double* XT,
   const double bb = (double)b;
   const int slot = prof_begin(s);
   if (b <= 16)
-    hipLaunchKernelGGL((chol_inv_kernel<CQR_CHOL_TG, 1>), dim3(1), dim3(CQR_CHOL_TG * CQR_CHOL_TG), 0, s, b, W, ldw,
-                       LT, XT, status, code, blk);
+    hipLaunchKernelGGL(chol_inv_kernel<1>, dim3(1), dim3(256), 0, s, b, W, ldw, LT, XT, status, code, blk);
   else if (b <= 32)
-    hipLaunchKernelGGL((chol_inv_kernel<CQR_CHOL_TG, 32 / CQR_CHOL_TG>), dim3(1), dim3(CQR_CHOL_TG * CQR_CHOL_TG), 0, s,
-                       b, W, ldw, LT, XT, status, code, blk);
+    hipLaunchKernelGGL(chol_inv_kernel<2>, dim3(1), dim3(256), 0, s, b, W, ldw, LT, XT, status, code, blk);
   else if (b <= 64)
-    hipLaunchKernelGGL((chol_inv_kernel<CQR_CHOL_TG, 64 / CQR_CHOL_TG>), dim3(1), dim3(CQR_CHOL_TG * CQR_CHOL_TG), 0, s,
-                       b, W, ldw, LT, XT, status, code, blk);
+    hipLaunchKernelGGL(chol_inv_kernel<4>, dim3(1), dim3(256), 0, s, b, W, ldw, LT, XT, status, code, blk);
   else
-    hipLaunchKernelGGL((chol_inv_kernel<CQR_CHOL_TG, 128 / CQR_CHOL_TG>), dim3(1), dim3(CQR_CHOL_TG * CQR_CHOL_TG), 0,
-                       s, b, W, ldw, LT, XT, status, code, blk);
+    hipLaunchKernelGGL(chol_inv_kernel<8>, dim3(1), dim3(256), 0, s, b, W, ldw, LT, XT, status, code, blk);
   hipError_t e = hipGetLastError();
   prof_end(slot, ROLE_CHOL, s, bb * bb * bb / 3.0, 8.0 * 3.0 * bb * bb);
   return e;

@@ -230,20 +230,21 @@ __device__ __forceinline__ int mc_index(int m, int k) {
 
 // Same contract as gemm_reg_kernel; requires K and kchunk multiples of 16,
 // 16-byte aligned A and B, even lda and ldb, and (for !TA) even M.
-template <int ROLE, bool TA, int MT, int NT, int S, int OCC>
-__global__ void __launch_bounds__(kThreads, OCC)
+template <int ROLE, bool TA, int MT, int NT, int S, int OCC, int WM = 2, int WN = 2>
+__global__ void __launch_bounds__(64 * WM * WN, OCC)
 gemm_dma_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A, int64_t lda,
                 const double* __restrict__ B, int64_t ldb, double beta, double* C, int64_t ldc, int64_t kchunk,
                 double* __restrict__ part, const int* __restrict__ gate) {
   static_assert(S == 2 || S == 3, "ring depth");
   if (gate != nullptr && *gate != 0) return;
   constexpr int KT = kDmaKT;
-  constexpr int WM = 2, WN = 2;
+  constexpr int NW = WM * WN;
   constexpr int WTM = MT / WM, WTN = NT / WN;
   constexpr int SM = WTM / 16, SN = WTN / 16;
   constexpr int ASTAGE = MT * KT, BSTAGE = NT * KT;                 // doubles per stage
-  constexpr int AINS = ASTAGE / 128 / 4, BINS = BSTAGE / 128 / 4;   // DMA instructions per wave per stage
+  constexpr int AINS = ASTAGE / 128 / NW, BINS = BSTAGE / 128 / NW; // DMA instructions per wave per stage
   static_assert(AINS >= 1 && BINS >= 1 && SM >= 1 && SN >= 1, "tile shape");
+  static_assert(AINS * 128 * NW == ASTAGE && BINS * 128 * NW == BSTAGE, "stage split over waves");
   __shared__ __attribute__((aligned(16))) double sA0[ASTAGE], sA1[ASTAGE], sA2[S > 2 ? ASTAGE : 2];
   __shared__ __attribute__((aligned(16))) double sB0[BSTAGE], sB1[BSTAGE], sB2[S > 2 ? BSTAGE : 2];
   auto slotA = [&](auto c) -> double* {
@@ -457,7 +458,7 @@ Plan plan_gemm(bool ta, int64_t M, int64_t N, int64_t K, const double* A, int64_
     int64_t max_split = K / (8 * kt);
     const int64_t by_cap = (int64_t)(part_cap / (size_t)(M * N));
     if (max_split > by_cap) max_split = by_cap;
-    if (max_split > 64) max_split = 64;
+    if (max_split > 512) max_split = 512;
     double best_eff = 0.0;
     for (int64_t sp = 1; sp <= (max_split < 1 ? 1 : max_split); ++sp) {
       const int64_t wgs = tiles * sp;
@@ -485,13 +486,13 @@ Plan plan_gemm(bool ta, int64_t M, int64_t N, int64_t K, const double* A, int64_
   return p;
 }
 
-template <int ROLE, bool TA, int MT, int NT, int S, int OCC>
+template <int ROLE, bool TA, int MT, int NT, int S, int OCC, int WM = 2, int WN = 2>
 hipError_t launch_dma(const Plan& p, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
                       const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double* part, const int* gate,
                       hipStream_t s) {
   const dim3 grid((unsigned)((M + MT - 1) / MT), (unsigned)((N + NT - 1) / NT), (unsigned)p.nsplit);
-  hipLaunchKernelGGL((gemm_dma_kernel<ROLE, TA, MT, NT, S, OCC>), grid, dim3(kThreads), 0, s, M, N, K, alpha, A,
-                     lda, B, ldb, beta, C, ldc, p.kchunk, part, gate);
+  hipLaunchKernelGGL((gemm_dma_kernel<ROLE, TA, MT, NT, S, OCC, WM, WN>), grid, dim3(64 * WM * WN), 0, s, M, N, K,
+                     alpha, A, lda, B, ldb, beta, C, ldc, p.kchunk, part, gate);
   return hipGetLastError();
 }
 
@@ -505,17 +506,19 @@ hipError_t launch_reg(const Plan& p, int64_t M, int64_t N, int64_t K, double alp
   return hipGetLastError();
 }
 
-// Ring depth / occupancy per DMA tile: 128x128 A^T B uses 2 slots at two
-// workgroups per CU; 128x128 A B uses 3 slots at one workgroup per CU; the
-// smaller shapes use 3 slots.
+// Ring depth / occupancy / wave grid per DMA tile (measured on gfx950 for the
+// q x b update and the s x b projection): 128x128 uses a 2-slot ring and 8
+// waves (4 x 2 of 32 x 64 for A^T B, 2 x 4 of 64 x 32 for A B), two waves per
+// SIMD; the smaller shapes use 4 waves and a 3-slot ring.
 template <int ROLE, bool TA>
 hipError_t launch(const Plan& p, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
                   const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double* part, const int* gate,
                   hipStream_t s) {
   if (p.dma) {
     if (p.mt == 128 && p.nt == 128) {
-      if (TA) return launch_dma<ROLE, TA, 128, 128, 2, 2>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
-      return launch_dma<ROLE, TA, 128, 128, 3, 1>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
+      if (TA)
+        return launch_dma<ROLE, TA, 128, 128, 2, 2, 4, 2>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
+      return launch_dma<ROLE, TA, 128, 128, 2, 2, 2, 4>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
     }
     if (p.mt == 128) return launch_dma<ROLE, TA, 128, 64, 3, 2>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
     if (p.nt == 128) return launch_dma<ROLE, TA, 64, 128, 3, 2>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
