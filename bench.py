@@ -12,6 +12,7 @@ same workload (cpu_baseline).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -37,6 +38,9 @@ def parse():
     p.add_argument("--seed", type=int, default=0)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-target-s", type=float, default=15.0, help="target oracle time for the CPU sample")
+    p.add_argument("--no-mixed", action="store_true", help="skip the BF16 + FP64-refinement form")
+    p.add_argument("--calib-copy-mib", type=int, default=0,
+                   help="before the run, copy this many MiB device-to-device once (reference kernel for HBM counters)")
     return p.parse_args()
 
 
@@ -63,6 +67,64 @@ def cpu_baseline(n: int, b: int, seed: int, target_s: float) -> dict:
     return {"value": round(fl / dt / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": "oracle CGS-QR (Algs. 3-5, FP64) of the first %d columns of the same %dx%d input, b=%d: "
                       "%.3e flops (Table 1) in %.2f s" % (r0, n, n, b, fl, dt)}
+
+
+def bench_mixed(cqr, torch, n: int, b: int, K: int, W: int, seed: int, fp64_ms: float) -> dict:
+    """BF16-MFMA CGS-QR + FP64 iterative refinement on the diagonally dominant
+    workload (off-diagonal U[-0.5, 0.5], diagonal = row sum of |.| + 1).
+    Value = the same nominal flop count as the FP64 form / (factor + refine)."""
+    from paper_2403_06218_amd import costmodel
+    dev = torch.device("cuda:0")
+    Y = cqr.colmajor(n, n, device=dev)
+    cqr.synth_uniform(Y, seed + 17, -0.5, 0.5)
+    Y.diagonal().zero_()
+    Y.diagonal().copy_(Y.abs().sum(dim=1) + 1.0)
+    rhs = torch.empty(n, dtype=torch.float64, device=dev)
+    cqr.synth_uniform(rhs.view(n, 1), seed + 18)
+    Q = cqr.colmajor(n, n, device=dev, dtype=torch.float32)
+    R = cqr.colmajor(n, n, device=dev, dtype=torch.float32)
+    import ctypes
+    nb = ctypes.c_size_t(0)
+    cqr._native.lib().cqr_workspace_size_mixed(n, n, b, cqr.PREC_BF16, ctypes.byref(nb))
+    work = torch.empty(int(nb.value), dtype=torch.uint8, device=dev)
+
+    def step():
+        _, _, info = cqr.qr_mixed(Y, b, Q=Q, R=R, work=work)
+        x, iters, res = cqr.solve_ir(Y, Q, R, rhs, maxiter=50, tol=16.0)
+        return info, iters, res
+
+    for _ in range(W):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = [step() for _ in range(K)]
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / K
+    t1 = time.perf_counter()
+    cqr.qr_mixed(Y, b, Q=Q, R=R, work=work)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t1
+    flops = costmodel.ca3(b, n, n) + costmodel.solve_flops(n)
+    return {"value": round(flops / el / 1e9, 2), "unit": "GFLOP/s", "ms_per_step": round(el * 1e3, 2),
+            "factor_ms": round(tf * 1e3, 2), "speedup_vs_fp64": round(fp64_ms / (el * 1e3), 3),
+            "ir_iterations": [o[1] for o in out], "hpl_scaled_residual": [o[2] for o in out],
+            "info": [o[0] for o in out], "dtype": "bf16 mfma (fp32 acc) + f64 panel + f64 refinement",
+            "workload": "n=%d, b=%d, off-diagonal U[-0.5,0.5], diagonal = row sum + 1, 1 RHS U[-1,1]" % (n, b)}
+
+
+def measured_traffic(role: str):
+    """HBM bytes per launch of `role` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, or None if the GEMM source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    src = os.path.join(ROOT, "paper_2403_06218_amd", "csrc", "gemm_f64.hip")
+    try:
+        meta = json.load(open(path))
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if meta.get("gemm_source_sha256") != digest or role not in meta.get("roles", {}):
+        return None
+    return meta["roles"][role]["hbm_bytes_per_launch"]
 
 
 def main():
@@ -92,6 +154,12 @@ def main():
     cqr.synth_uniform(rhs.view(n, 1), args.seed + 1)
     R = cqr.colmajor(n, n, device=dev)
     work = torch.empty(cqr.workspace_size(n, n, b), dtype=torch.uint8, device=dev)
+    if args.calib_copy_mib > 0:
+        src = torch.ones(args.calib_copy_mib << 17, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     swork = torch.empty(max(256, 8 * n), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 
@@ -129,8 +197,11 @@ def main():
     dom = max(roles, key=lambda k: roles[k]["ms"])
     d = roles[dom]
     achieved = d["flops"] / (d["ms"] * 1e-3) / 1e12
+    traffic = measured_traffic(dom)
     roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3), "peak": PEAK_FP64_MFMA_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_MFMA_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_MFMA_TFLOPS, 4),
+                "traffic": round(traffic) if traffic else None, "traffic_unit": "HBM bytes per launch",
+                "algorithmic_bytes_per_launch": round(d["bytes"] / d["launches"]),
                 "launches_per_step": d["launches"] // K, "avg_launch_ms": round(d["ms"] / d["launches"], 4)}
     breakdown = {k: {"ms_per_step": round(v["ms"] / K, 3), "launches_per_step": v["launches"] // K,
                      "tflops": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 3) if v["flops"] else None}
@@ -162,6 +233,10 @@ def main():
         "checks": {"info": infos, "hpl_scaled_residual_sampled_rows": float(hpl_rows),
                    "max_offdiag_QtQ_sampled_cols": float(orth)},
     }
+    if not args.no_mixed:
+        del Ys
+        torch.cuda.empty_cache()
+        out["mixed"] = bench_mixed(cqr, torch, n, b, K, W, args.seed, ms_step)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, b, args.seed, args.cpu_target_s)
     print(json.dumps(out), flush=True)

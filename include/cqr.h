@@ -39,6 +39,9 @@ extern "C" {
 #define CQR_ERR_WORKSPACE (-101)   /* work == NULL or work_bytes below the required size     */
 #define CQR_ERR_HIP_BASE (-1000)   /* -1000 - hipError_t: a HIP launch or runtime call failed */
 
+/* Precision forms of cqr_factor_mixed. */
+#define CQR_PREC_BF16 1 /* projections and updates on BF16 MFMA with FP32 accumulation */
+
 /* Bits of the per-block flags written by cqr_factor. */
 #define CQR_FLAG_FALLBACK 1 /* the block's Cholesky factorisation broke down; redone by CGS2 */
 #define CQR_FLAG_ZERO_COL 2 /* the block holds a column with no component outside the earlier ones */
@@ -113,6 +116,39 @@ int cqr_solve_workspace_size(int64_t n, size_t* bytes);
  */
 int cqr_solve(int64_t n, const double* Q, int64_t ldq, const double* R, int64_t ldr, double* x, void* work,
               size_t work_bytes, void* stream);
+
+/*
+ * Low-precision form of cqr_factor (not in the paper, which computes in IEEE
+ * double): CGS-QR (Algorithm 3) with the projections H = P^T Q and the updates
+ * Q -= P H of Algorithm 5 (S1/S2, S6/S7) on BF16 matrix cores with FP32
+ * accumulation (prec = CQR_PREC_BF16); the working block, its Gram matrices,
+ * Cholesky factors and triangular solves stay in FP64.
+ *   Y, ldy   in (device, FP64, 16-byte aligned, even ldy): q x r; not modified.
+ *   Q, ldq   out (FP32): q x r with Q^T Q ~ I to BF16 accuracy.
+ *   R, ldr   out (FP32): r x r upper triangular.
+ *   b        block width: a multiple of 16, at most 128.
+ *   info     host, may be NULL: 0, or the 1-based index of the first block whose
+ *            Cholesky factorisation broke down; then Q and R are not valid (this
+ *            form has no CGS2 fallback; use cqr_factor).
+ * Synchronises the stream once at the end.
+ */
+int cqr_workspace_size_mixed(int64_t q, int64_t r, int64_t b, int prec, size_t* bytes);
+int cqr_factor_mixed(int64_t q, int64_t r, int64_t b, int prec, const double* Y, int64_t ldy, float* Q, int64_t ldq,
+                     float* R, int64_t ldr, void* work, size_t work_bytes, int32_t* info, void* stream);
+
+/*
+ * FP64 iterative refinement of Y x = rhs (square, n x n) with the factors of
+ * cqr_factor_mixed: x_0 = 0; d = R^{-1} Q^T r (FP32 factors, FP64
+ * arithmetic); x += d; r = rhs - Y x in FP64; stop when the HPL scaled residual
+ * ||r||_inf / (||Y||_inf ||x||_inf n eps) < tol or after maxiter updates.
+ *   x        out (device, FP64, length n).
+ *   iters, scaled_resid   host, may be NULL: updates done, final residual.
+ * Synchronises the stream once per iteration.
+ */
+int cqr_solve_ir_workspace_size(int64_t n, size_t* bytes);
+int cqr_solve_ir(int64_t n, const double* Y, int64_t ldy, const float* Q, int64_t ldq, const float* R, int64_t ldr,
+                 const double* rhs, double* x, int32_t maxiter, double tol, int32_t* iters, double* scaled_resid,
+                 void* work, size_t work_bytes, void* stream);
 
 /*
  * Launch timing.  While enabled, every kernel launch the library makes is

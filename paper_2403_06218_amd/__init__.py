@@ -20,8 +20,10 @@ from ._native import CqrError
 
 FLAG_FALLBACK = 1
 FLAG_ZERO_COL = 2
+PREC_BF16 = 1
 
-__all__ = ["colmajor", "workspace_size", "qr", "orth", "orth_against", "solve", "synth_uniform",
+__all__ = ["colmajor", "workspace_size", "qr", "orth", "orth_against", "solve", "qr_mixed", "solve_ir",
+           "synth_uniform",
            "prof_enable", "prof_reset", "prof_query", "prof_names", "CqrError", "version"]
 
 
@@ -138,6 +140,56 @@ def solve(Q: torch.Tensor, R: torch.Tensor, rhs: torch.Tensor, work: torch.Tenso
                                  _stream())
     _native.check(rc, "cqr_solve")
     return x
+
+
+def qr_mixed(Y: torch.Tensor, b: int, prec: int = PREC_BF16, Q: torch.Tensor | None = None,
+             R: torch.Tensor | None = None, work: torch.Tensor | None = None):
+    """Low-precision CGS-QR of column-major FP64 Y (not modified): BF16 MFMA
+    projections/updates, FP64 panel.  Returns (Q (FP32), R (FP32), info)."""
+    q, r = Y.shape
+    if Q is None:
+        Q = colmajor(q, r, device=Y.device, dtype=torch.float32)
+    if R is None:
+        R = colmajor(r, r, device=Y.device, dtype=torch.float32)
+    n = ctypes.c_size_t(0)
+    _native.check(_native.lib().cqr_workspace_size_mixed(q, r, b, prec, ctypes.byref(n)), "cqr_workspace_size_mixed")
+    if work is None:
+        work = _workspace(int(n.value), Y.device)
+    info = ctypes.c_int32(0)
+    rc = _native.lib().cqr_factor_mixed(q, r, b, prec, _ptr(Y), _ld(Y, "Y"), _ptr(Q), _ld32(Q, "Q"), _ptr(R),
+                                        _ld32(R, "R"), _ptr(work), work.numel(), ctypes.byref(info), _stream())
+    _native.check(rc, "cqr_factor_mixed")
+    return Q, R, int(info.value)
+
+
+def solve_ir(Y: torch.Tensor, Q: torch.Tensor, R: torch.Tensor, rhs: torch.Tensor, maxiter: int = 50,
+             tol: float = 16.0, work: torch.Tensor | None = None):
+    """FP64 iterative refinement with the low-precision factors.  Returns (x, iters, scaled_residual)."""
+    n = Y.shape[0]
+    x = torch.empty(n, dtype=torch.float64, device=Y.device)
+    nb = ctypes.c_size_t(0)
+    _native.check(_native.lib().cqr_solve_ir_workspace_size(n, ctypes.byref(nb)), "cqr_solve_ir_workspace_size")
+    if work is None:
+        work = _workspace(int(nb.value), Y.device)
+    rhs = rhs.contiguous()
+    it = ctypes.c_int32(0)
+    res = ctypes.c_double(0)
+    rc = _native.lib().cqr_solve_ir(n, _ptr(Y), _ld(Y, "Y"), _ptr(Q), _ld32(Q, "Q"), _ptr(R), _ld32(R, "R"), _ptr(rhs),
+                                    _ptr(x), maxiter, tol, ctypes.byref(it), ctypes.byref(res), _ptr(work),
+                                    work.numel(), _stream())
+    _native.check(rc, "cqr_solve_ir")
+    return x, int(it.value), float(res.value)
+
+
+def _ld32(t: torch.Tensor, name: str) -> int:
+    if t.dtype != torch.float32:
+        raise TypeError("%s must be float32" % name)
+    if not t.is_cuda:
+        raise TypeError("%s must be a GPU tensor" % name)
+    rows, cols = t.shape
+    if t.stride(0) != 1 and rows > 1:
+        raise ValueError("%s must be column-major (stride(0) == 1); use colmajor()" % name)
+    return max(t.stride(1) if cols > 1 else rows, rows, 1)
 
 
 def synth_uniform(A: torch.Tensor, seed: int, lo: float = -1.0, hi: float = 1.0) -> torch.Tensor:

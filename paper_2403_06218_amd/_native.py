@@ -26,6 +26,12 @@ CQR_SIGNATURES = {
                          ctypes.c_int),
     "cqr_solve_workspace_size": ([i64, szp], ctypes.c_int),
     "cqr_solve": ([i64, vp, i64, vp, i64, vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
+    "cqr_workspace_size_mixed": ([i64, i64, i64, ctypes.c_int, szp], ctypes.c_int),
+    "cqr_factor_mixed": ([i64, i64, i64, ctypes.c_int, vp, i64, vp, i64, vp, i64, vp, ctypes.c_size_t, i32p, vp],
+                         ctypes.c_int),
+    "cqr_solve_ir_workspace_size": ([i64, szp], ctypes.c_int),
+    "cqr_solve_ir": ([i64, vp, i64, vp, i64, vp, i64, vp, vp, ctypes.c_int32, dbl, i32p, dblp, vp, ctypes.c_size_t, vp],
+                     ctypes.c_int),
     "cqr_prof_enable": ([ctypes.c_int], ctypes.c_int),
     "cqr_prof_reset": ([], ctypes.c_int),
     "cqr_prof_query": ([ctypes.c_char_p, i64p, dblp, dblp, dblp], ctypes.c_int),

@@ -1,0 +1,322 @@
+// BF16 GEMM on the CDNA4 matrix cores (v_mfma_f32_16x16x32_bf16, FP32
+// accumulation) for the low-precision form of the factorisation: the
+// projections H = P^T Q and the updates Q -= P H of Algorithm 5 (S1/S2,
+// S6/S7), which carry almost all of its flops (Table 1).
+//
+// Both operands are "k-contiguous" BF16 matrices: C (M x N) = alpha * A^T B
+// + beta * C with A stored K x M and B stored K x N, column-major.  (For the
+// update the caller passes the transposed copy of P.)  The host pads K to a
+// multiple of 64 with zeros, aligns every column to 16 bytes and gives the
+// leading dimensions in multiples of 8 elements.
+//
+// Tiling: an MT x NT tile per workgroup of WM x WN wave64s; K is walked in
+// 64-deep stages copied global -> LDS by the LDS-DMA load
+// (global_load_lds_dwordx4, 16 bytes = 8 BF16 per lane) into an S-slot ring
+// with one barrier per stage.  In LDS a column of a stage is 8 chunks of 8
+// consecutive k; chunk c of column x sits at slot c ^ ((x >> 1) & 7), so the
+// 16 lanes of a 128-bit operand read (16 columns, one chunk) hit 16 distinct
+// 16-byte bank groups.
+//
+// MFMA lane layout (measured on gfx950): lane l supplies A(l%16, 8(l/16)+e)
+// and B(8(l/16)+e, l%16), e = 0..7, and holds C(4(l/16)+v, l%16) in
+// accumulator element v.
+#include <type_traits>
+
+#include "internal.h"
+
+namespace cqr {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_void;
+
+constexpr int kBKT = 64;  // k per stage
+
+__device__ __forceinline__ void dma16(const void* g, void* lds_base) {
+  __builtin_amdgcn_global_load_lds(g, (lds_void*)lds_base, 16, 0, 0);
+}
+
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// Byte offset of chunk c (8 k values) of column x in a stage.
+__device__ __forceinline__ int chunk_off(int c, int x) { return x * 128 + 16 * (c ^ ((x >> 1) & 7)); }
+
+// OUT: 0 = FP32 partial sums into part (split-K), 1 = FP32 C, 2 = FP64 C.
+template <int ROLE, int OUT, int MT, int NT, int S, int WM, int WN, int OCC>
+__global__ void __launch_bounds__(64 * WM * WN, OCC)
+gemm_bf16_kernel(int64_t M, int64_t N, int64_t K, float alpha, const __bf16* __restrict__ A, int64_t lda,
+                 const __bf16* __restrict__ B, int64_t ldb, float beta, void* C, int64_t ldc, int64_t kchunk,
+                 float* __restrict__ part, const int* __restrict__ gate) {
+  static_assert(S == 2 || S == 3, "ring depth");
+  if (gate != nullptr && *gate != 0) return;
+  constexpr int NW = WM * WN;
+  constexpr int WTM = MT / WM, WTN = NT / WN;
+  constexpr int SM = WTM / 16, SN = WTN / 16;
+  constexpr int ASTAGE = MT * kBKT * 2, BSTAGE = NT * kBKT * 2;   // bytes per stage
+  constexpr int AINS = ASTAGE / 1024 / NW, BINS = BSTAGE / 1024 / NW;
+  static_assert(AINS >= 1 && BINS >= 1 && AINS * 1024 * NW == ASTAGE && BINS * 1024 * NW == BSTAGE, "stage split");
+  static_assert(SM >= 1 && SN >= 1, "wave tile");
+  __shared__ __attribute__((aligned(16))) char sA0[ASTAGE], sA1[ASTAGE], sA2[S > 2 ? ASTAGE : 16];
+  __shared__ __attribute__((aligned(16))) char sB0[BSTAGE], sB1[BSTAGE], sB2[S > 2 ? BSTAGE : 16];
+  auto slotA = [&](auto c) -> char* {
+    if constexpr (c.value == 0) return sA0;
+    else if constexpr (c.value == 1) return sA1;
+    else return sA2;
+  };
+  auto slotB = [&](auto c) -> char* {
+    if constexpr (c.value == 0) return sB0;
+    else if constexpr (c.value == 1) return sB1;
+    else return sB2;
+  };
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave % WM, wn = wave / WM;
+  const int li = lane & 15, lg = lane >> 4;
+  const int64_t m0 = (int64_t)blockIdx.x * MT;
+  const int64_t n0 = (int64_t)blockIdx.y * NT;
+  const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+  const int64_t kend = (K < kbeg + kchunk) ? K : kbeg + kchunk;
+  const int nst = (kend > kbeg) ? (int)((kend - kbeg) / kBKT) : 0;
+
+  // Element offsets of this lane's DMA chunks from the stage origin; columns
+  // past the matrix are clamped (their values reach only unstored outputs).
+  int64_t aoff[AINS], boff[BINS];
+#pragma unroll
+  for (int t = 0; t < AINS; ++t) {
+    const int p = (wave * AINS + t) * 64 + lane;
+    const int x = p / 8, c = (p % 8) ^ ((x >> 1) & 7);
+    const int64_t m = (m0 + x < M) ? m0 + x : M - 1;
+    aoff[t] = 8 * c + m * lda;
+  }
+#pragma unroll
+  for (int t = 0; t < BINS; ++t) {
+    const int p = (wave * BINS + t) * 64 + lane;
+    const int x = p / 8, c = (p % 8) ^ ((x >> 1) & 7);
+    const int64_t n = (n0 + x < N) ? n0 + x : N - 1;
+    boff[t] = 8 * c + n * ldb;
+  }
+
+  auto issue = [&](int st, auto slot) {
+    const int64_t k0 = kbeg + (int64_t)st * kBKT;
+    char* la = slotA(slot);
+    char* lb = slotB(slot);
+#pragma unroll
+    for (int t = 0; t < AINS; ++t) dma16(A + k0 + aoff[t], la + (wave * AINS + t) * 1024);
+#pragma unroll
+    for (int t = 0; t < BINS; ++t) dma16(B + k0 + boff[t], lb + (wave * BINS + t) * 1024);
+  };
+
+  f4 acc[SM][SN];
+#pragma unroll
+  for (int i = 0; i < SM; ++i)
+#pragma unroll
+    for (int j = 0; j < SN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  auto compute = [&](auto slot) {
+    const char* cA = slotA(slot);
+    const char* cB = slotB(slot);
+#pragma unroll
+    for (int h = 0; h < kBKT / 32; ++h) {
+      const int c = 4 * h + lg;  // chunk (8 k values) this lane supplies
+      bf16x8 af[SM], bf[SN];
+#pragma unroll
+      for (int i = 0; i < SM; ++i)
+        af[i] = *(const bf16x8*)(cA + chunk_off(c, wm * WTM + i * 16 + li));
+#pragma unroll
+      for (int j = 0; j < SN; ++j)
+        bf[j] = *(const bf16x8*)(cB + chunk_off(c, wn * WTN + j * 16 + li));
+#pragma unroll
+      for (int i = 0; i < SM; ++i)
+#pragma unroll
+        for (int j = 0; j < SN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+  };
+
+  constexpr int PER_STAGE = AINS + BINS;
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  auto step = [&](int st, auto cur, auto nxt) {
+    if (st + S - 2 < nst) wait_vmcnt<(S - 2) * PER_STAGE>();
+    else wait_vmcnt<0>();
+    __syncthreads();
+    if (st + S - 1 < nst) issue(st + S - 1, nxt);
+    compute(cur);
+  };
+  if (nst > 0) issue(0, I0{});
+  if (S > 2 && nst > 1) issue(1, I1{});
+  for (int st = 0; st < nst; st += S) {
+    if constexpr (S == 2) {
+      step(st, I0{}, I1{});
+      if (st + 1 < nst) step(st + 1, I1{}, I0{});
+    } else {
+      step(st, I0{}, I2{});
+      if (st + 1 < nst) step(st + 1, I1{}, I0{});
+      if (st + 2 < nst) step(st + 2, I2{}, I1{});
+    }
+  }
+
+  const int64_t zoff = (int64_t)blockIdx.z * M * N;
+#pragma unroll
+  for (int i = 0; i < SM; ++i)
+#pragma unroll
+    for (int j = 0; j < SN; ++j) {
+      const int64_t n = n0 + wn * WTN + j * 16 + li;
+      const int64_t mb = m0 + wm * WTM + i * 16 + 4 * lg;
+      if (n >= N) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t m = mb + v;
+        if (m >= M) continue;
+        const float val = acc[i][j][v];
+        if constexpr (OUT == 0) {
+          part[zoff + m + n * M] = val;
+        } else if constexpr (OUT == 1) {
+          float* Cf = (float*)C;
+          float c = alpha * val;
+          if (beta != 0.f) c += beta * Cf[m + n * ldc];
+          Cf[m + n * ldc] = c;
+        } else {
+          double* Cd = (double*)C;
+          double c = (double)alpha * (double)val;
+          if (beta != 0.f) c += (double)beta * Cd[m + n * ldc];
+          Cd[m + n * ldc] = c;
+        }
+      }
+    }
+}
+
+// C (FP32 or FP64) = alpha * sum_z part[z] + beta * C, in split order.
+template <typename TC>
+__global__ void __launch_bounds__(256)
+splitk_reduce_f32_kernel(int64_t M, int64_t N, int nsplit, const float* __restrict__ part, float alpha, float beta,
+                         TC* C, int64_t ldc, const int* __restrict__ gate) {
+  if (gate != nullptr && *gate != 0) return;
+  const int64_t total = M * N;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    TC s = 0;
+    for (int z = 0; z < nsplit; ++z) s += (TC)part[(int64_t)z * total + idx];
+    const int64_t m = idx % M, n = idx / M;
+    TC c = (TC)alpha * s;
+    if (beta != 0.f) c += (TC)beta * C[m + n * ldc];
+    C[m + n * ldc] = c;
+  }
+}
+
+template <int ROLE, int OUT, int MT, int NT>
+hipError_t launch_bf16(int64_t M, int64_t N, int64_t K, float alpha, const __bf16* A, int64_t lda, const __bf16* B,
+                       int64_t ldb, float beta, void* C, int64_t ldc, int64_t kchunk, int nsplit, float* part,
+                       const int* gate, hipStream_t s) {
+  constexpr int WM = (MT == 128 && NT == 128) ? 2 : 2;
+  constexpr int WN = (MT == 128 && NT == 128) ? 4 : 2;
+  constexpr int OCC = (MT == 128 && NT == 128) ? 1 : 2;
+  const dim3 grid((unsigned)((M + MT - 1) / MT), (unsigned)((N + NT - 1) / NT), (unsigned)nsplit);
+  hipLaunchKernelGGL((gemm_bf16_kernel<ROLE, OUT, MT, NT, 3, WM, WN, OCC>), grid, dim3(64 * WM * WN), 0, s, M, N, K,
+                     alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, gate);
+  return hipGetLastError();
+}
+
+template <int ROLE, int OUT>
+hipError_t launch_bf16_tile(int64_t M, int64_t N, int64_t K, float alpha, const __bf16* A, int64_t lda,
+                            const __bf16* B, int64_t ldb, float beta, void* C, int64_t ldc, int64_t kchunk, int nsplit,
+                            float* part, const int* gate, hipStream_t s) {
+  if (M > 64 && N > 64)
+    return launch_bf16<ROLE, OUT, 128, 128>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, nsplit, part, gate,
+                                            s);
+  if (M > 64)
+    return launch_bf16<ROLE, OUT, 128, 64>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, nsplit, part, gate,
+                                           s);
+  if (N > 64)
+    return launch_bf16<ROLE, OUT, 64, 128>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, nsplit, part, gate,
+                                           s);
+  return launch_bf16<ROLE, OUT, 64, 64>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, nsplit, part, gate, s);
+}
+
+int64_t bf16_tiles(int64_t M, int64_t N) {
+  const int64_t mt = M > 64 ? 128 : 64, nt = N > 64 ? 128 : 64;
+  return ((M + mt - 1) / mt) * ((N + nt - 1) / nt);
+}
+
+}  // namespace
+
+bool gemm_bf16_supported(const void* A, int64_t lda, const void* B, int64_t ldb, int64_t K) {
+  return !(reinterpret_cast<uintptr_t>(A) & 15) && !(reinterpret_cast<uintptr_t>(B) & 15) && lda % 8 == 0 &&
+         ldb % 8 == 0 && K % kBKT == 0;
+}
+
+hipError_t gemm_bf16_tn(Role role, int64_t M, int64_t N, int64_t K, float alpha, const __bf16* A, int64_t lda,
+                        const __bf16* B, int64_t ldb, float beta, void* C, int64_t ldc, bool c_is_f64, float* part,
+                        size_t part_cap, const int* gate, hipStream_t s, double flops) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  if (!gemm_bf16_supported(A, lda, B, ldb, K)) return hipErrorInvalidValue;
+  // Split-K through FP32 partial sums: fill whole rounds of 256 resident
+  // workgroups, each walking at least 4 stages, within the partial buffer.
+  int nsplit = 1;
+  if (part != nullptr) {
+    const int64_t tiles = bf16_tiles(M, N);
+    int64_t max_split = K / (4 * kBKT);
+    const int64_t by_cap = (int64_t)(part_cap / (size_t)(M * N));
+    if (max_split > by_cap) max_split = by_cap;
+    if (max_split > 256) max_split = 256;
+    double best = 0.0;
+    for (int64_t sp = 1; sp <= (max_split < 1 ? 1 : max_split); ++sp) {
+      const int64_t wgs = tiles * sp;
+      const int64_t rounds = (wgs + 255) / 256;
+      const double eff = (double)wgs / (double)(rounds * 256);
+      if (eff > best + 0.02) {
+        best = eff;
+        nsplit = (int)sp;
+      }
+    }
+  }
+  int64_t kchunk = K > 0 ? K : kBKT;
+  if (nsplit > 1) {
+    kchunk = (K + nsplit - 1) / nsplit;
+    kchunk = (kchunk + kBKT - 1) / kBKT * kBKT;
+    nsplit = (int)((K + kchunk - 1) / kchunk);
+  }
+  const double bytes = 2.0 * ((double)K * M + (double)K * N) + (c_is_f64 ? 8.0 : 4.0) * (double)M * N *
+                                                                  (beta != 0.f ? 2.0 : 1.0);
+  const int slot = prof_begin(s);
+  hipError_t e;
+  if (nsplit > 1)
+    e = (role == ROLE_UPDATE)
+            ? launch_bf16_tile<ROLE_UPDATE, 0>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, nsplit, part,
+                                               gate, s)
+            : launch_bf16_tile<ROLE_PROJ, 0>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, nsplit, part, gate,
+                                             s);
+  else if (c_is_f64)
+    e = (role == ROLE_UPDATE)
+            ? launch_bf16_tile<ROLE_UPDATE, 2>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, 1, part, gate, s)
+            : launch_bf16_tile<ROLE_PROJ, 2>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, 1, part, gate, s);
+  else
+    e = (role == ROLE_UPDATE)
+            ? launch_bf16_tile<ROLE_UPDATE, 1>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, 1, part, gate, s)
+            : launch_bf16_tile<ROLE_PROJ, 1>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, 1, part, gate, s);
+  prof_end(slot, role, s, flops, bytes);
+  if (e != hipSuccess || nsplit == 1) return e;
+  const int64_t total = M * N;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  const int slot2 = prof_begin(s);
+  if (c_is_f64)
+    hipLaunchKernelGGL(splitk_reduce_f32_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, M, N, nsplit, part,
+                       alpha, beta, (double*)C, ldc, gate);
+  else
+    hipLaunchKernelGGL(splitk_reduce_f32_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s, M, N, nsplit, part,
+                       alpha, beta, (float*)C, ldc, gate);
+  e = hipGetLastError();
+  prof_end(slot2, ROLE_REDUCE, s, 0.0, 4.0 * (double)total * (nsplit + (beta != 0.f ? 2 : 1)));
+  return e;
+}
+
+}  // namespace cqr

@@ -43,6 +43,15 @@ hipError_t gemm_nn(Role role, int64_t M, int64_t N, int64_t K, double alpha, con
                    const double* B, int64_t ldb, double beta, double* C, int64_t ldc, const int* gate,
                    hipStream_t s, double flops);
 
+// BF16 GEMM with FP32 accumulation: C (M x N) = alpha * A^T B + beta * C with
+// A (K x M) and B (K x N) BF16, k-contiguous.  C is FP64 when c_is_f64, else
+// FP32 (then split over K through `part`, capacity part_cap floats).
+// Requires 16-byte aligned A and B, lda and ldb multiples of 8, K a multiple of 64.
+bool gemm_bf16_supported(const void* A, int64_t lda, const void* B, int64_t ldb, int64_t K);
+hipError_t gemm_bf16_tn(Role role, int64_t M, int64_t N, int64_t K, float alpha, const __bf16* A, int64_t lda,
+                        const __bf16* B, int64_t ldb, float beta, void* C, int64_t ldc, bool c_is_f64, float* part,
+                        size_t part_cap, const int* gate, hipStream_t s, double flops);
+
 // Lower Cholesky W = L L^T of a b x b SPD matrix (b <= 128) and the inverse of
 // L, in one workgroup.  Writes LT = L^T and XT = (L^{-1})^T (both b x b,
 // leading dimension b, upper triangular with zero strictly-lower part).  On a

@@ -1,0 +1,488 @@
+// Low-precision form of the factorisation and the FP64 iterative refinement.
+//
+// cqr_factor_mixed runs CGS-QR (Algorithms 3-5) with the projections
+// (Alg. 5 S1/S6) and updates (S2/S7) on BF16 MFMA with FP32 accumulation,
+// while the working block, its Gram matrices, Cholesky factors and TRSMs stay
+// in FP64.  Finished columns are kept in BF16 twice (column-major for the
+// projections' A^T, transposed for the updates' A) and returned as FP32 Q; R
+// is returned in FP32.  Y itself is read, never written, so that the
+// refinement can compute residuals against it.
+//
+// cqr_solve_ir: x_0 = 0, then repeatedly d = R^{-1} Q^T r (FP32 factors, FP64
+// arithmetic), x += d, r = rhs - Y x (FP64), until the HPL scaled residual
+// ||r||_inf / (||Y||_inf ||x||_inf n eps) is below the tolerance.
+#include <cstring>
+
+#include "internal.h"
+#include "../../include/cqr.h"
+
+namespace cqr {
+namespace {
+
+#define MX_TRY(expr)                                          \
+  do {                                                        \
+    hipError_t e_ = (expr);                                   \
+    if (e_ != hipSuccess) return CQR_ERR_HIP_BASE - (int)e_;  \
+  } while (0)
+
+size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+int64_t up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+struct MixedWork {
+  int* status;
+  double *W, *LT1, *XT1, *LT2, *XT2, *Rjj;  // b x b
+  double* Qj;       // q x b working block (FP64)
+  double* T;        // q x b after the first pass
+  double* H;        // r x b projections, first pass (FP64)
+  double* Hb;       // r x b projections, second pass
+  __bf16* P16;      // qp x rp: finished columns, column-major (ld qp)
+  __bf16* P16T;     // rp x qp: finished columns transposed (ld rp)
+  __bf16* B16;      // qp x b: BF16 copy of the block being projected (ld qp)
+  __bf16* H16;      // rp x b: BF16 copy of a projection (ld rp)
+  float* part;      // split-K partial sums
+  size_t part_cap;
+  int64_t qp, rp;
+};
+
+size_t mixed_layout(int64_t q, int64_t r, int64_t b, char* base, MixedWork* w) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base ? base + off : nullptr;
+    off += a256(bytes);
+    return p;
+  };
+  MixedWork tmp;
+  MixedWork* o = w ? w : &tmp;
+  o->qp = up(q > 0 ? q : 1, 64);
+  o->rp = up(r > 0 ? r : 1, 64);
+  const size_t bb = (size_t)b * b * 8, qb = (size_t)q * b * 8;
+  o->status = (int*)take(64);
+  o->W = (double*)take(bb);
+  o->LT1 = (double*)take(bb);
+  o->XT1 = (double*)take(bb);
+  o->LT2 = (double*)take(bb);
+  o->XT2 = (double*)take(bb);
+  o->Rjj = (double*)take(bb);
+  o->Qj = (double*)take(qb);
+  o->T = (double*)take(qb);
+  o->H = (double*)take((size_t)o->rp * b * 8);
+  o->Hb = (double*)take((size_t)o->rp * b * 8);
+  o->P16 = (__bf16*)take((size_t)o->qp * o->rp * 2);
+  o->P16T = (__bf16*)take((size_t)o->rp * o->qp * 2);
+  o->B16 = (__bf16*)take((size_t)o->qp * b * 2);
+  o->H16 = (__bf16*)take((size_t)o->rp * b * 2);
+  o->part_cap = (size_t)16 << 20;
+  o->part = (float*)take(o->part_cap * 4);
+  return off;
+}
+
+// dst (bf16, rows_pad x cols, ld ldd) = bf16(src (rows x cols, lds)); rows
+// rows..rows_pad-1 are zero.
+__global__ void __launch_bounds__(256)
+to_bf16_kernel(int64_t rows, int64_t rows_pad, int64_t cols, const double* __restrict__ src, int64_t lds,
+               __bf16* __restrict__ dst, int64_t ldd, const int* __restrict__ gate) {
+  if (gate != nullptr && *gate != 0) return;
+  const int64_t total = rows_pad * cols;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx % rows_pad, j = idx / rows_pad;
+    dst[i + j * ldd] = (i < rows) ? (__bf16)src[i + j * lds] : (__bf16)0.0f;
+  }
+}
+
+// A finished block Qj (q x w, FP64): Q32[:, c0:c0+w] = float(Qj),
+// P16[:, c0:c0+w] = bf16(Qj), P16T[c0:c0+w, :] = bf16(Qj)^T (through an LDS
+// tile so that both the column-major and the transposed writes coalesce).
+__global__ void __launch_bounds__(256)
+finish_block_kernel(int64_t q, int w, const double* __restrict__ Qj, int64_t ldj, float* __restrict__ Q32,
+                    int64_t ldq, __bf16* __restrict__ P16, int64_t ldp, __bf16* __restrict__ P16T, int64_t ldpt,
+                    int64_t c0, const int* __restrict__ gate) {
+  if (gate != nullptr && *gate != 0) return;
+  __shared__ __bf16 tile[64][65];
+  const int64_t i0 = (int64_t)blockIdx.x * 64;
+  const int j0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+  for (int jj = ty; jj < 64; jj += 4) {
+    const int64_t i = i0 + tx;
+    const int j = j0 + jj;
+    if (i < q && j < w) {
+      const double v = Qj[i + (int64_t)j * ldj];
+      Q32[i + (c0 + j) * ldq] = (float)v;
+      const __bf16 h = (__bf16)v;
+      P16[i + (c0 + j) * ldp] = h;
+      tile[jj][tx] = h;
+    }
+  }
+  __syncthreads();
+  for (int ii = ty; ii < 64; ii += 4) {
+    const int64_t i = i0 + ii;
+    const int j = j0 + tx;
+    if (i < q && j < w) P16T[(c0 + j) + i * ldpt] = tile[tx][ii];
+  }
+}
+
+// R32[0:rows, cols] = float(src) for a rows x cols FP64 block.
+__global__ void __launch_bounds__(256)
+to_f32_kernel(int64_t rows, int64_t cols, const double* __restrict__ src, int64_t lds, float* __restrict__ dst,
+              int64_t ldd, const int* __restrict__ gate) {
+  if (gate != nullptr && *gate != 0) return;
+  const int64_t total = rows * cols;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx % rows, j = idx / rows;
+    dst[i + j * ldd] = (float)src[i + j * lds];
+  }
+}
+
+__global__ void __launch_bounds__(256) fill_kernel(int64_t n, char* __restrict__ p) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+__global__ void __launch_bounds__(256) zero_f32_kernel(int64_t rows, int64_t cols, float* __restrict__ X, int64_t ldx) {
+  const int64_t total = rows * cols;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x)
+    X[idx % rows + (idx / rows) * ldx] = 0.f;
+}
+
+unsigned grid_of(int64_t total) {
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  if (blocks < 1) blocks = 1;
+  return (unsigned)blocks;
+}
+
+// ---------------------------------------------------------------- refinement
+
+// part[c][i] = sum over columns j in chunk c of |Y(i, j)| (absval) or Y(i, j) x_j.
+template <bool ABS>
+__global__ void __launch_bounds__(256)
+gemv_n_part_kernel(int64_t n, const double* __restrict__ Y, int64_t ldy, const double* __restrict__ x, int64_t chunk,
+                   double* __restrict__ part) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (i >= n) return;
+  const int64_t j0 = c * chunk, j1 = (j0 + chunk < n) ? j0 + chunk : n;
+  double acc = 0.0;
+  for (int64_t j = j0; j < j1; ++j) {
+    const double y = Y[i + j * ldy];
+    acc += ABS ? fabs(y) : y * x[j];
+  }
+  part[c * n + i] = acc;
+}
+
+// r = rhs - sum_c part[c] (or the row sums themselves when rhs == nullptr);
+// out[0] = max |r_i|, computed by one workgroup per 256 rows into blockmax.
+__global__ void __launch_bounds__(256)
+residual_kernel(int64_t n, int nchunk, const double* __restrict__ part, const double* __restrict__ rhs,
+                double* __restrict__ r, double* __restrict__ blockmax) {
+  __shared__ double red[256];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double v = 0.0;
+  if (i < n) {
+    double s = 0.0;
+    for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * n + i];
+    v = rhs ? rhs[i] - s : s;
+    if (r) r[i] = v;
+  }
+  red[threadIdx.x] = fabs(v);
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) blockmax[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) max_kernel(int64_t n, const double* __restrict__ v, double* __restrict__ out) {
+  __shared__ double red[256];
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) m = fmax(m, fabs(v[i]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+// y = Q^T v with FP32 Q, FP64 v and accumulation: one wave per column.
+__global__ void __launch_bounds__(256)
+gemv_t_f32_kernel(int64_t n, const float* __restrict__ Q, int64_t ldq, const double* __restrict__ v,
+                  double* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= n) return;
+  const float* qc = Q + j * ldq;
+  double acc = 0.0;
+  for (int64_t i = lane; i < n; i += 64) acc += (double)qc[i] * v[i];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) y[j] = acc;
+}
+
+constexpr int kNB = 64;
+
+// One launch per 64-row block I (last first): rows of blocks above subtract
+// R[rows, I] x_I, and the workgroup that owns block I-1 then back-substitutes
+// its diagonal block.  x_I is final when the launch for block I starts.
+__global__ void __launch_bounds__(kNB)
+trsv_f32_step_kernel(int64_t n, const float* __restrict__ R, int64_t ldr, double* __restrict__ y, int64_t i0) {
+  // blockIdx.x covers rows [blockIdx.x * 64, +64) of the region [0, i0).
+  __shared__ double xs[kNB];
+  __shared__ double sR[kNB][kNB + 1];
+  const int t = threadIdx.x;
+  const int64_t nb = (n - i0 < kNB) ? n - i0 : kNB;  // width of block I (already solved)
+  if (t < nb) xs[t] = y[i0 + t];
+  __syncthreads();
+  const int64_t r0 = (int64_t)blockIdx.x * kNB;
+  const int64_t row = r0 + t;
+  double v = 0.0;
+  if (row < i0) {
+    double acc = 0.0;
+    for (int c = 0; c < nb; ++c) acc += (double)R[row + (i0 + c) * ldr] * xs[c];
+    v = y[row] - acc;
+  }
+  // The last workgroup holds block I-1 = rows [i0 - 64, i0): solve it.
+  if (r0 + kNB == i0) {
+    for (int c = 0; c < kNB; ++c) sR[t][c] = (double)R[(r0 + t) + (r0 + c) * ldr];
+    __syncthreads();
+    __shared__ double xv;
+    for (int i = kNB - 1; i >= 0; --i) {
+      if (t == i) {
+        v = v / sR[i][i];
+        xv = v;
+      }
+      __syncthreads();
+      if (t < i) v -= sR[t][i] * xv;
+      __syncthreads();
+    }
+  }
+  if (row < i0) y[row] = v;
+}
+
+// Back substitution of the last (possibly partial) block [i0, n) alone.
+__global__ void __launch_bounds__(kNB)
+trsv_f32_last_kernel(int64_t n, const float* __restrict__ R, int64_t ldr, double* __restrict__ y, int64_t i0) {
+  __shared__ double sR[kNB][kNB + 1];
+  __shared__ double xv;
+  const int t = threadIdx.x;
+  const int nb = (int)(n - i0);
+  for (int c = 0; c < nb; ++c)
+    if (t < nb) sR[t][c] = (double)R[(i0 + t) + (i0 + c) * ldr];
+  double v = (t < nb) ? y[i0 + t] : 0.0;
+  __syncthreads();
+  for (int i = nb - 1; i >= 0; --i) {
+    if (t == i) {
+      v = v / sR[i][i];
+      xv = v;
+    }
+    __syncthreads();
+    if (t < i) v -= sR[t][i] * xv;
+    __syncthreads();
+  }
+  if (t < nb) y[i0 + t] = v;
+}
+
+__global__ void __launch_bounds__(256) axpy_kernel(int64_t n, const double* __restrict__ d, double* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) x[i] += d[i];
+}
+
+// ---------------------------------------------------------------- factor
+
+// One column block of the mixed factorisation (see the file comment).
+int mixed_block(int64_t q, int64_t w, int64_t s, const double* Yj, int64_t ldy, float* Q32, int64_t ldq, float* R32,
+                int64_t ldr, const MixedWork& ws, int blk, hipStream_t st) {
+  const int* gate = ws.status;
+  const double dq = (double)q, dw = (double)w, ds = (double)s;
+  const int64_t sp = up(s, 64);
+  MX_TRY(copy_matrix(q, w, Yj, ldy, ws.Qj, q, gate, st));
+  for (int pass = 0; pass < 2; ++pass) {
+    double* X = pass == 0 ? ws.Qj : ws.T;      // block being orthogonalised
+    double* Hx = pass == 0 ? ws.H : ws.Hb;     // its projection (s x w, ld rp)
+    if (s > 0) {
+      hipLaunchKernelGGL(to_bf16_kernel, dim3(grid_of(ws.qp * w)), dim3(256), 0, st, q, ws.qp, w, X, q, ws.B16, ws.qp,
+                         gate);
+      MX_TRY(hipGetLastError());
+      // S1/S6: H = P^T X  (BF16 x BF16 -> FP32, reduced into FP64)
+      MX_TRY(gemm_bf16_tn(ROLE_PROJ, s, w, ws.qp, 1.0f, ws.P16, ws.qp, ws.B16, ws.qp, 0.0f, Hx, ws.rp, true, ws.part,
+                          ws.part_cap, gate, st, 2.0 * dw * dq * ds));
+      hipLaunchKernelGGL(to_bf16_kernel, dim3(grid_of(sp * w)), dim3(256), 0, st, s, sp, w, Hx, ws.rp, ws.H16, ws.rp,
+                         gate);
+      MX_TRY(hipGetLastError());
+      // S2/S7: X -= P H  (A = P^T stored k-contiguous, K = s padded with zeros)
+      MX_TRY(gemm_bf16_tn(ROLE_UPDATE, q, w, sp, -1.0f, ws.P16T, ws.rp, ws.H16, ws.rp, 1.0f, X, q, true, nullptr, 0,
+                          gate, st, 2.0 * dw * dq * ds));
+    }
+    // S3/S8, S4/S9, S5/S10 in FP64.
+    MX_TRY(gemm_tn(ROLE_GRAM, w, w, q, 1.0, X, q, X, q, 0.0, ws.W, w, (double*)ws.part, ws.part_cap / 2, gate, st,
+                   (s > 0 ? 2.0 : 1.0) * dw * dw * dq));
+    MX_TRY(chol_inv((int)w, ws.W, w, pass == 0 ? ws.LT1 : ws.LT2, pass == 0 ? ws.XT1 : ws.XT2, ws.status, pass + 1,
+                    blk, st));
+    MX_TRY(gemm_nn(ROLE_TRSM, q, w, w, 1.0, X, q, pass == 0 ? ws.XT1 : ws.XT2, w, 0.0, pass == 0 ? ws.T : ws.Qj, q,
+                   gate, st, dw * dw * dq));
+  }
+  // S11 R_jj = Lb^T L^T, S12 H = H + Hb L^T, in FP64; then R (FP32) and the
+  // finished columns.
+  MX_TRY(gemm_nn(ROLE_SMALL, w, w, w, 1.0, ws.LT2, w, ws.LT1, w, 0.0, ws.Rjj, w, gate, st, dw * dw * dw));
+  if (s > 0) {
+    MX_TRY(gemm_nn(ROLE_SMALL, s, w, w, 1.0, ws.Hb, ws.rp, ws.LT1, w, 1.0, ws.H, ws.rp, gate, st, dw * ds));
+    hipLaunchKernelGGL(to_f32_kernel, dim3(grid_of(s * w)), dim3(256), 0, st, s, w, ws.H, ws.rp, R32 + s * ldr, ldr,
+                       gate);
+    MX_TRY(hipGetLastError());
+  }
+  hipLaunchKernelGGL(to_f32_kernel, dim3(grid_of(w * w)), dim3(256), 0, st, w, w, ws.Rjj, w, R32 + s + s * ldr, ldr,
+                     gate);
+  MX_TRY(hipGetLastError());
+  hipLaunchKernelGGL(finish_block_kernel, dim3((unsigned)((q + 63) / 64), (unsigned)((w + 63) / 64)), dim3(256), 0, st,
+                     q, (int)w, ws.Qj, q, Q32, ldq, ws.P16, ws.qp, ws.P16T, ws.rp, s, gate);
+  MX_TRY(hipGetLastError());
+  return CQR_OK;
+}
+
+}  // namespace
+}  // namespace cqr
+
+using namespace cqr;
+
+extern "C" {
+
+int cqr_workspace_size_mixed(int64_t q, int64_t r, int64_t b, int prec, size_t* bytes) {
+  if (q < 0) return -1;
+  if (r < 0 || r > q) return -2;
+  if (b < 1) return -3;
+  if (b > 128 || b % 16 != 0) return CQR_ERR_UNSUPPORTED;
+  if (prec != CQR_PREC_BF16) return CQR_ERR_UNSUPPORTED;
+  if (!bytes) return -5;
+  *bytes = mixed_layout(q, r, b, nullptr, nullptr);
+  return CQR_OK;
+}
+
+int cqr_factor_mixed(int64_t q, int64_t r, int64_t b, int prec, const double* Y, int64_t ldy, float* Q, int64_t ldq,
+                     float* R, int64_t ldr, void* work, size_t work_bytes, int32_t* info, void* stream) {
+  if (q < 0) return -1;
+  if (r < 0 || r > q) return -2;
+  if (b < 1) return -3;
+  if (b > 128 || b % 16 != 0) return CQR_ERR_UNSUPPORTED;
+  if (prec != CQR_PREC_BF16) return CQR_ERR_UNSUPPORTED;
+  if (!Y && q * r > 0) return -5;
+  if (ldy < (q > 1 ? q : 1) || (ldy & 1)) return ldy < q ? -6 : CQR_ERR_UNSUPPORTED;
+  if (!Q && q * r > 0) return -7;
+  if (ldq < (q > 1 ? q : 1)) return -8;
+  if (!R && r > 0) return -9;
+  if (ldr < (r > 1 ? r : 1)) return -10;
+  if (reinterpret_cast<uintptr_t>(Y) & 15) return CQR_ERR_UNSUPPORTED;
+  if (info) *info = 0;
+  if (r == 0) return CQR_OK;
+  const size_t need = mixed_layout(q, r, b, nullptr, nullptr);
+  if (!work || work_bytes < need) return CQR_ERR_WORKSPACE;
+  MixedWork ws;
+  mixed_layout(q, r, b, (char*)work, &ws);
+  hipStream_t st = (hipStream_t)stream;
+  // Zero the whole workspace: the BF16 buffers rely on zero padding and on
+  // not-yet-finished columns reading as zero.
+  hipLaunchKernelGGL(fill_kernel, dim3(grid_of((int64_t)need)), dim3(256), 0, st, (int64_t)need, (char*)work);
+  MX_TRY(hipGetLastError());
+  hipLaunchKernelGGL(zero_f32_kernel, dim3(grid_of(r * r)), dim3(256), 0, st, r, r, R, ldr);
+  MX_TRY(hipGetLastError());
+  const int64_t k = (r + b - 1) / b;
+  for (int64_t blk = 0; blk < k; ++blk) {
+    const int64_t s = blk * b;
+    const int64_t w = (r - s < b) ? r - s : b;
+    const int rc = mixed_block(q, w, s, Y + s * ldy, ldy, Q, ldq, R, ldr, ws, (int)blk, st);
+    if (rc) return rc;
+  }
+  int stv[2] = {0, 0};
+  MX_TRY(hipStreamSynchronize(st));
+  MX_TRY(hipMemcpy(stv, ws.status, sizeof(stv), hipMemcpyDeviceToHost));
+  if (stv[0] != 0 && info) *info = stv[1] + 1;
+  return CQR_OK;
+}
+
+int cqr_solve_ir_workspace_size(int64_t n, size_t* bytes) {
+  if (n < 0) return -1;
+  if (!bytes) return -2;
+  const int64_t nchunk = 16;
+  *bytes = a256((size_t)(nchunk + 4) * (size_t)(n > 0 ? n : 1) * 8) + a256((size_t)((n + 255) / 256 + 8) * 8);
+  return CQR_OK;
+}
+
+int cqr_solve_ir(int64_t n, const double* Y, int64_t ldy, const float* Q, int64_t ldq, const float* R, int64_t ldr,
+                 const double* rhs, double* x, int32_t maxiter, double tol, int32_t* iters, double* scaled_resid,
+                 void* work, size_t work_bytes, void* stream) {
+  if (n < 0) return -1;
+  if (!Y && n > 0) return -2;
+  if (ldy < (n > 1 ? n : 1)) return -3;
+  if (!Q && n > 0) return -4;
+  if (ldq < (n > 1 ? n : 1)) return -5;
+  if (!R && n > 0) return -6;
+  if (ldr < (n > 1 ? n : 1)) return -7;
+  if (!rhs && n > 0) return -8;
+  if (!x && n > 0) return -9;
+  if (maxiter < 1) return -10;
+  if (!(tol > 0.0)) return -11;
+  if (iters) *iters = 0;
+  if (scaled_resid) *scaled_resid = 0.0;
+  if (n == 0) return CQR_OK;
+  size_t need = 0;
+  cqr_solve_ir_workspace_size(n, &need);
+  if (!work || work_bytes < need) return CQR_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  const int nchunk = 16;
+  const int64_t chunk = (n + nchunk - 1) / nchunk;
+  double* part = (double*)work;                 // nchunk x n
+  double* r = part + (int64_t)nchunk * n;       // residual
+  double* c = r + n;                            // Q^T r, then d
+  double* bm = (double*)((char*)work + a256((size_t)(nchunk + 4) * n * 8));  // block maxima, then scalars
+  const int64_t nblk = (n + 255) / 256;
+  double* scal = bm + nblk;                     // [0] |Y|_inf [1] |r|_inf [2] |x|_inf
+  const dim3 gpart((unsigned)nblk, (unsigned)nchunk);
+  // ||Y||_inf once.
+  hipLaunchKernelGGL(gemv_n_part_kernel<true>, gpart, dim3(256), 0, st, n, Y, ldy, (const double*)nullptr, chunk, part);
+  MX_TRY(hipGetLastError());
+  hipLaunchKernelGGL(residual_kernel, dim3((unsigned)nblk), dim3(256), 0, st, n, nchunk, part, (const double*)nullptr,
+                     (double*)nullptr, bm);
+  MX_TRY(hipGetLastError());
+  hipLaunchKernelGGL(max_kernel, dim3(1), dim3(256), 0, st, nblk, bm, scal + 0);
+  MX_TRY(hipGetLastError());
+  // x = 0, r = rhs.
+  MX_TRY(zero_matrix(n, 1, x, n, st));
+  MX_TRY(copy_matrix(n, 1, rhs, n, r, n, nullptr, st));
+  const double eps = 2.220446049250313e-16;
+  for (int it = 1; it <= maxiter; ++it) {
+    // d = R^{-1} Q^T r
+    hipLaunchKernelGGL(gemv_t_f32_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, n, Q, ldq, r, c);
+    MX_TRY(hipGetLastError());
+    const int64_t ilast = ((n - 1) / kNB) * kNB;
+    hipLaunchKernelGGL(trsv_f32_last_kernel, dim3(1), dim3(kNB), 0, st, n, R, ldr, c, ilast);
+    MX_TRY(hipGetLastError());
+    for (int64_t i0 = ilast; i0 > 0; i0 -= kNB) {
+      hipLaunchKernelGGL(trsv_f32_step_kernel, dim3((unsigned)(i0 / kNB)), dim3(kNB), 0, st, n, R, ldr, c, i0);
+      MX_TRY(hipGetLastError());
+    }
+    hipLaunchKernelGGL(axpy_kernel, dim3((unsigned)nblk), dim3(256), 0, st, n, c, x);
+    MX_TRY(hipGetLastError());
+    // r = rhs - Y x, ||r||_inf, ||x||_inf
+    hipLaunchKernelGGL(gemv_n_part_kernel<false>, gpart, dim3(256), 0, st, n, Y, ldy, x, chunk, part);
+    MX_TRY(hipGetLastError());
+    hipLaunchKernelGGL(residual_kernel, dim3((unsigned)nblk), dim3(256), 0, st, n, nchunk, part, rhs, r, bm);
+    MX_TRY(hipGetLastError());
+    hipLaunchKernelGGL(max_kernel, dim3(1), dim3(256), 0, st, nblk, bm, scal + 1);
+    MX_TRY(hipGetLastError());
+    hipLaunchKernelGGL(max_kernel, dim3(1), dim3(256), 0, st, n, x, scal + 2);
+    MX_TRY(hipGetLastError());
+    double h[3];
+    MX_TRY(hipMemcpyAsync(h, scal, sizeof(h), hipMemcpyDeviceToHost, st));
+    MX_TRY(hipStreamSynchronize(st));
+    const double res = h[1] / (h[0] * h[2] * (double)n * eps);
+    if (iters) *iters = it;
+    if (scaled_resid) *scaled_resid = res;
+    if (res < tol) break;
+  }
+  return CQR_OK;
+}
+
+}  // extern "C"

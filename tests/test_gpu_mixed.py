@@ -1,0 +1,90 @@
+"""The low-precision form (BF16 MFMA projections/updates, FP64 panel) and the
+FP64 iterative refinement, through the C ABI, against the CPU oracle.
+
+Tolerances.  The BF16 products round each input to 8 significand bits
+(u = 2^-8) and accumulate in FP32, so the mixed factors agree with the FP64
+QR to O(u) relative to ||Y|| (bounds below use 8u * sqrt(b) scaled by
+kappa); they are only a preconditioner.  The refined solution must satisfy the
+FP64 HPL bar ||Yx - b||_inf / (||Y||_inf ||x||_inf n eps) < 16, and then agrees
+with the oracle's FP64 solution to 16 kappa n eps relative (forward error of a
+backward-stable solve).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2403_06218_amd as cqr
+from paper_2403_06218_amd import inputs
+from gpu_util import EPS, hpl_ratio, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+U_BF16 = 2.0 ** -8
+
+
+def _host32(T):
+    return np.asfortranarray(T.t().cpu().numpy().T).astype(np.float64)
+
+
+@pytest.mark.parametrize("n,b", [(512, 64), (512, 128), (1000, 64), (4096, 128)])
+def test_mixed_factor_against_oracle(n, b):
+    """Diagonally dominant input (off-diagonal U[-0.5, 0.5], diagonal = row sum + 1)."""
+    Y = inputs.diag_dominant(n, seed=n)
+    Yd = to_dev(Y)
+    Q, R, info = cqr.qr_mixed(Yd, b)
+    torch.cuda.synchronize()
+    assert info == 0
+    Qh, Rh = _host32(Q), _host32(R)
+    # Y is read only.
+    assert np.array_equal(to_host(Yd), Y)
+    assert np.array_equal(np.tril(Rh, -1), np.zeros_like(Rh))
+    assert (np.diag(Rh) > 0).all()
+    kappa = np.linalg.cond(Y)
+    bound = 8 * U_BF16 * np.sqrt(b) * kappa
+    Qo, Ro = oracle.householder_qr(Y)
+    assert np.abs(Qh - Qo).max() < bound
+    assert np.abs(Rh - Ro).max() < bound * np.abs(Ro).max()
+    assert np.linalg.norm(Y - Qh @ Rh) / np.linalg.norm(Y) < bound
+    assert np.abs(Qh.T @ Qh - np.eye(n)).max() < bound
+
+
+@pytest.mark.parametrize("n,b", [(512, 64), (2048, 128), (4096, 128)])
+def test_mixed_ir_solve_reaches_fp64_residual(n, b):
+    Y = inputs.diag_dominant(n, seed=7 + n)
+    rhs = inputs.uniform_vector(n, seed=8 + n)
+    Yd = to_dev(Y)
+    Q, R, info = cqr.qr_mixed(Yd, b)
+    assert info == 0
+    x, iters, res = cqr.solve_ir(Yd, Q, R, torch.from_numpy(rhs).cuda(), maxiter=50, tol=16.0)
+    torch.cuda.synchronize()
+    xh = x.cpu().numpy()
+    assert res < 16 and 1 <= iters < 50
+    assert hpl_ratio(Y, xh, rhs) < 16
+    Qo, Ro = oracle.householder_qr(Y)
+    xo, rc = oracle.qr_solve(Qo, Ro, rhs)
+    assert rc == 0
+    kappa = np.linalg.cond(Y)
+    assert np.abs(xh - xo).max() < 16 * kappa * n * EPS * np.abs(xo).max()
+
+
+def test_mixed_ragged_and_small_blocks():
+    """r not a multiple of b, b = 16, q > r (tall)."""
+    Y = inputs.diag_dominant(300, seed=3)[:, :200].copy(order="F")
+    Q, R, info = cqr.qr_mixed(to_dev(Y), 48)
+    torch.cuda.synchronize()
+    assert info == 0
+    Qh, Rh = _host32(Q), _host32(R)
+    assert np.linalg.norm(Y - Qh @ Rh) / np.linalg.norm(Y) < 8 * U_BF16 * np.sqrt(48) * np.linalg.cond(Y)
+    Q2, R2, info2 = cqr.qr_mixed(to_dev(Y), 16)
+    assert info2 == 0
+    np.testing.assert_allclose(_host32(R2), Rh, atol=8 * U_BF16 * np.abs(Rh).max())
+
+
+def test_mixed_rejects_unsupported_block():
+    Y = to_dev(inputs.diag_dominant(64, seed=1))
+    with pytest.raises(cqr.CqrError):
+        cqr.qr_mixed(Y, 100)
