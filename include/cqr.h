@@ -151,6 +151,72 @@ int cqr_solve_ir(int64_t n, const double* Y, int64_t ldy, const float* Q, int64_
                  void* work, size_t work_bytes, void* stream);
 
 /*
+ * Batched form: CGS-QR (Algorithms 3-5) and the solve x = R^{-1} Q^T b of
+ * `count` independent square systems A_i x_i = b_i of uneven size
+ * 1 <= n_i <= 512, in FP64 or FP32, one workgroup per matrix in persistent
+ * launches (one per size bucket of the plan; see cqr_batched_plan_*).  Every
+ * array below is in device memory and indexed by i; every call is
+ * stream-ordered and asynchronous (capturable in a hipGraph: no host
+ * synchronisation, no memset, no allocation).
+ *   dtype    CQR_F64 (double) or CQR_F32 (float): the element type of every
+ *            A_i, R_i, B_i, and the arithmetic of the whole path.
+ *   n        n_i.
+ *   A, lda   column-major n_i x n_i, lda_i >= n_i.  In: A_i; out: Q_i (in place).
+ *   R, ldr   out: n_i x n_i upper triangular R_i (strictly lower part zero).
+ *   B        may be NULL (factor only).  In: b_i (length n_i); out: x_i.
+ *   info     out: 0, the 1-based first block whose Cholesky broke down and was
+ *            redone by CGS2, or -1 for an entry with an invalid size, leading
+ *            dimension or NULL pointer (that entry is left untouched).
+ *   flags    may be NULL; out: CQR_FLAG_FALLBACK | CQR_FLAG_ZERO_COL bits.
+ *   work     device workspace of cqr_batched_workspace_size(count) bytes.
+ * Block width and kernel instance come from the plan for n_i's bucket.  An
+ * exactly dependent column gives a zero Q column and R_jj = 0, and then x_i
+ * holds infinities or NaNs.
+ * Returns 0, -1..-9 for an invalid argument, CQR_ERR_WORKSPACE, or
+ * -1000 - hipError_t.
+ */
+#define CQR_F64 0
+#define CQR_F32 1
+int cqr_batched_workspace_size(int64_t count, size_t* bytes);
+int cqr_batched_factor_solve(int64_t count, int dtype, const int32_t* n, void* const* A, const int32_t* lda,
+                             void* const* R, const int32_t* ldr, void* const* B, int32_t* info, int32_t* flags,
+                             void* work, size_t work_bytes, void* stream);
+
+/*
+ * Kernel instances of the batched form: id -> element type, largest n,
+ * block width and waves per workgroup.  CQR_ERR_UNSUPPORTED past the last id.
+ */
+int cqr_batched_instance(int32_t id, int32_t* dtype, int32_t* nmax, int32_t* bw, int32_t* waves);
+
+/*
+ * Plan of the batched form for one element type: nbuckets (<= 8) size buckets
+ * with ascending upper bounds hi[b] (bucket b holds hi[b-1] < n <= hi[b]; the
+ * last bound is the largest n accepted) and the instance inst[b] that serves
+ * each (its nmax >= hi[b]).  The library starts with a default plan; the
+ * package's autotuner measures the instances and sets a new one.  Host arrays.
+ */
+int cqr_batched_plan_get(int dtype, int32_t* nbuckets, int32_t* hi, int32_t* inst);
+int cqr_batched_plan_set(int dtype, int32_t nbuckets, const int32_t* hi, const int32_t* inst);
+
+/*
+ * Adjoint of the batched solve (reverse mode): with A_i = Q_i R_i the stored
+ * factors and x_i = A_i^{-1} b_i from cqr_batched_factor_solve, and g_i the
+ * upstream gradient dL/dx_i,
+ *   lambda_i = A_i^{-T} g_i = Q_i (R_i^{-T} g_i),  dA_i = -lambda_i x_i^T,
+ *   db_i = lambda_i.
+ * Device arrays indexed by i, as in cqr_batched_factor_solve: n, Q/ldq, R/ldr
+ * (inputs), x, g (inputs, length n_i), dA/ldda (output, column-major n_i x n_i),
+ * db (output, length n_i).  dtype CQR_F64 or CQR_F32 for every array.
+ * Entries with n_i outside [1, 512], a leading dimension below n_i or a NULL
+ * pointer are skipped.  No workspace; asynchronous on `stream`.  A zero R_ii
+ * gives infinities or NaNs in that entry's outputs.
+ * Returns 0, -1..-12 for an invalid argument, or -1000 - hipError_t.
+ */
+int cqr_batched_solve_backward(int64_t count, int dtype, const int32_t* n, void* const* Q, const int32_t* ldq,
+                               void* const* R, const int32_t* ldr, void* const* x, void* const* g, void* const* dA,
+                               const int32_t* ldda, void* const* db, void* stream);
+
+/*
  * Launch timing.  While enabled, every kernel launch the library makes is
  * bracketed by a pair of hipEvents on its stream.  cqr_prof_query synchronises
  * those events and returns, for the kernel role `name` (see cqr_prof_name),

@@ -32,6 +32,13 @@ CQR_SIGNATURES = {
     "cqr_solve_ir_workspace_size": ([i64, szp], ctypes.c_int),
     "cqr_solve_ir": ([i64, vp, i64, vp, i64, vp, i64, vp, vp, ctypes.c_int32, dbl, i32p, dblp, vp, ctypes.c_size_t, vp],
                      ctypes.c_int),
+    "cqr_batched_workspace_size": ([i64, szp], ctypes.c_int),
+    "cqr_batched_factor_solve": ([i64, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp],
+                                 ctypes.c_int),
+    "cqr_batched_solve_backward": ([i64, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+    "cqr_batched_instance": ([ctypes.c_int32, i32p, i32p, i32p, i32p], ctypes.c_int),
+    "cqr_batched_plan_get": ([ctypes.c_int, i32p, i32p, i32p], ctypes.c_int),
+    "cqr_batched_plan_set": ([ctypes.c_int, ctypes.c_int32, i32p, i32p], ctypes.c_int),
     "cqr_prof_enable": ([ctypes.c_int], ctypes.c_int),
     "cqr_prof_reset": ([], ctypes.c_int),
     "cqr_prof_query": ([ctypes.c_char_p, i64p, dblp, dblp, dblp], ctypes.c_int),

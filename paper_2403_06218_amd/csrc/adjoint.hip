@@ -1,0 +1,158 @@
+// Adjoint of the solve x = A^{-1} b with A = Q R (stored factors of the
+// batched form): for an upstream gradient g = dL/dx,
+//   lambda = A^{-T} g = Q (R^{-T} g),   dL/dA = -lambda x^T,   dL/db = lambda.
+// One workgroup per matrix: the triangular solve R^T z = g is blocked by 32
+// (a dot product per column against the finished part of z, then the 32 x 32
+// triangle in one wave with readlane), lambda = Q z one row per thread, and the
+// rank-1 product written column by column (coalesced).  HBM-bound on reading
+// Q and R and writing dA.
+#include "internal.h"
+#include "../../include/cqr.h"
+
+namespace cqr {
+namespace {
+
+template <typename T>
+__device__ __forceinline__ T rlane(T x, int l);
+template <>
+__device__ __forceinline__ double rlane<double>(double x, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+  return __hiloint2double(hi, lo);
+}
+template <>
+__device__ __forceinline__ float rlane<float>(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
+template <typename T>
+__device__ __forceinline__ T wsum(T x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+constexpr int kAdjNMax = 512;
+constexpr int kAdjThreads = 512;
+
+struct AdjArgs {
+  const int32_t* n;
+  void* const* Q;
+  const int32_t* ldq;
+  void* const* R;
+  const int32_t* ldr;
+  void* const* x;
+  void* const* g;
+  void* const* dA;
+  const int32_t* ldda;
+  void* const* db;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(AdjArgs a) {
+  constexpr int NW = kAdjThreads / 64;
+  __shared__ T sz[kAdjNMax];  // g, then z = R^{-T} g
+  __shared__ T sx[kAdjNMax];
+  __shared__ T sl[kAdjNMax];  // lambda
+  const int m = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n = a.n[m];
+  const int ldq = a.ldq[m], ldr = a.ldr[m], ldda = a.ldda[m];
+  if (n < 1 || n > kAdjNMax || ldq < n || ldr < n || ldda < n) return;
+  const T* Q = (const T*)a.Q[m];
+  const T* R = (const T*)a.R[m];
+  const T* x = (const T*)a.x[m];
+  const T* g = (const T*)a.g[m];
+  T* dA = (T*)a.dA[m];
+  T* db = (T*)a.db[m];
+  if (!Q || !R || !x || !g || !dA || !db) return;
+  for (int r = tid; r < n; r += kAdjThreads) {
+    sz[r] = g[r];
+    sx[r] = x[r];
+  }
+  __syncthreads();
+  // R^T z = g, column block by column block.
+  for (int s = 0; s < n; s += 32) {
+    const int w = min(32, n - s);
+    if (s > 0) {
+      for (int i = wave; i < w; i += NW) {
+        const T* rc = R + (size_t)(s + i) * ldr;
+        T d = T(0);
+        for (int p = lane; p < s; p += 64) d += rc[p] * sz[p];
+        d = wsum(d);
+        if (lane == 0) sz[s + i] -= d;
+      }
+      __syncthreads();
+    }
+    if (wave == 0) {
+      // Lane j holds column j of the diagonal block: rcol[p] = R(s + p, s + j).
+      T rcol[32];
+      const T* rc = R + (size_t)(s + lane) * ldr + s;
+#pragma unroll
+      for (int p = 0; p < 32; ++p) rcol[p] = (lane < w && p < w) ? rc[p] : T(0);
+      T gj = (lane < w) ? sz[s + lane] : T(0);
+#pragma unroll
+      for (int p = 0; p < 32; ++p) {
+        if (p < w) {
+          const T zp = rlane(gj, p) / rlane(rcol[p], p);
+          if (lane == p) gj = zp;
+          else if (lane > p) gj -= rcol[p] * zp;
+        }
+      }
+      if (lane < w) sz[s + lane] = gj;
+    }
+    __syncthreads();
+  }
+  // lambda = Q z; db = lambda.
+  for (int r = tid; r < n; r += kAdjThreads) {
+    T d = T(0);
+    for (int c = 0; c < n; ++c) d += Q[(size_t)r + (size_t)c * ldq] * sz[c];
+    sl[r] = d;
+    db[r] = d;
+  }
+  __syncthreads();
+  // dA = -lambda x^T.
+  for (int c = 0; c < n; ++c) {
+    const T xc = sx[c];
+    T* col = dA + (size_t)c * ldda;
+    for (int r = tid; r < n; r += kAdjThreads) col[r] = -sl[r] * xc;
+  }
+}
+
+}  // namespace
+}  // namespace cqr
+
+using namespace cqr;
+
+extern "C" {
+
+int cqr_batched_solve_backward(int64_t count, int dtype, const int32_t* n, void* const* Q, const int32_t* ldq,
+                               void* const* R, const int32_t* ldr, void* const* x, void* const* g, void* const* dA,
+                               const int32_t* ldda, void* const* db, void* stream) {
+  if (count < 0 || count > INT32_MAX) return -1;
+  if (dtype != CQR_F64 && dtype != CQR_F32) return -2;
+  if (count == 0) return CQR_OK;
+  if (!n) return -3;
+  if (!Q) return -4;
+  if (!ldq) return -5;
+  if (!R) return -6;
+  if (!ldr) return -7;
+  if (!x) return -8;
+  if (!g) return -9;
+  if (!dA) return -10;
+  if (!ldda) return -11;
+  if (!db) return -12;
+  hipStream_t st = (hipStream_t)stream;
+  AdjArgs aa{n, Q, ldq, R, ldr, x, g, dA, ldda, db};
+  const int slot = prof_begin(st);
+  if (dtype == CQR_F64)
+    hipLaunchKernelGGL(adjoint_kernel<double>, dim3((unsigned)count), dim3(kAdjThreads), 0, st, aa);
+  else
+    hipLaunchKernelGGL(adjoint_kernel<float>, dim3((unsigned)count), dim3(kAdjThreads), 0, st, aa);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return CQR_ERR_HIP_BASE - (int)e;
+  prof_end(slot, ROLE_ADJOINT, st, 0.0, 0.0);
+  return CQR_OK;
+}
+
+}  // extern "C"

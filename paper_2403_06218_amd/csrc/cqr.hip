@@ -56,7 +56,8 @@ hipEvent_t pool_get() {
 }
 
 const char* const kRoleNames[ROLE_COUNT] = {"proj", "update", "gram", "trsm", "small", "reduce",
-                                            "chol", "copy", "gemv", "trsv_diag", "trsv_update"};
+                                            "chol", "copy", "gemv", "trsv_diag", "trsv_update",
+                                            "batch", "batch_setup", "adjoint"};
 }  // namespace
 
 const char* role_name(int role) { return (role >= 0 && role < ROLE_COUNT) ? kRoleNames[role] : nullptr; }

@@ -22,6 +22,9 @@ enum Role : int {
   ROLE_GEMV,        // solve: c = Q^T rhs
   ROLE_TRSV_DIAG,   // solve: diagonal-block back substitution
   ROLE_TRSV_UPD,    // solve: off-diagonal update
+  ROLE_BATCH,       // batched form: whole factorisation + solve, one workgroup per matrix
+  ROLE_BATCH_SETUP, // batched form: size sort and bucket boundaries
+  ROLE_ADJOINT,     // adjoint of the solve
   ROLE_COUNT
 };
 

@@ -105,3 +105,30 @@ def batch_sizes(count: int, lo: int, hi: int, seed: int) -> np.ndarray:
     """``count`` integers drawn uniformly from [lo, hi] (inclusive)."""
     u = uniform01(seed, np.arange(count, dtype=np.uint64))
     return (lo + np.floor(u * (hi - lo + 1))).astype(np.int64)
+
+
+def packed_offsets(sizes) -> np.ndarray:
+    """Start of each n_i x n_i matrix in a packed column-major batch (ld = n_i)."""
+    sizes = np.asarray(sizes, dtype=np.int64)
+    off = np.zeros(sizes.size + 1, dtype=np.int64)
+    np.cumsum(sizes * sizes, out=off[1:])
+    return off
+
+
+def packed_matrix(sizes, i: int, seed: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    """Matrix i of a packed batch filled as one stream: element (r, c) of matrix
+    i is stream element off_i + r + c n_i (the layout of a flat device buffer
+    filled by the GPU generator as a single column)."""
+    sizes = np.asarray(sizes, dtype=np.int64)
+    n = int(sizes[i])
+    o = int(packed_offsets(sizes)[i])
+    t = np.arange(o, o + n * n, dtype=np.uint64)
+    return np.asfortranarray(_affine(uniform01(seed, t), lo, hi).reshape((n, n)).T)
+
+
+def packed_vector(sizes, i: int, seed: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    """Vector i (length n_i) of a packed batch of vectors filled as one stream."""
+    sizes = np.asarray(sizes, dtype=np.int64)
+    o = int(sizes[:i].sum())
+    t = np.arange(o, o + int(sizes[i]), dtype=np.uint64)
+    return _affine(uniform01(seed, t), lo, hi)

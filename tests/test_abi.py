@@ -4,6 +4,7 @@ import os
 import re
 
 import pytest
+import torch
 
 from paper_2403_06218_amd import _native
 
@@ -67,3 +68,40 @@ def test_profiler_role_names():
     names = cqr.prof_names()
     assert "update" in names and "proj" in names and "chol" in names
     assert cqr.prof_query("update")["launches"] == 0
+
+
+def test_batched_validation_and_plan():
+    lib = _native.lib()
+    v = ctypes.c_void_p(0x1000)  # never dereferenced: every case fails validation first
+    nb = ctypes.c_size_t(0)
+    assert lib.cqr_batched_workspace_size(-1, ctypes.byref(nb)) == -1
+    assert lib.cqr_batched_workspace_size(10000, ctypes.byref(nb)) == 0 and nb.value >= 40000
+    assert lib.cqr_batched_factor_solve(0, 0, None, None, None, None, None, None, None, None, None, 0, None) == 0
+    assert lib.cqr_batched_factor_solve(-1, 0, v, v, v, v, v, v, v, v, v, 1 << 20, None) == -1
+    assert lib.cqr_batched_factor_solve(4, 2, v, v, v, v, v, v, v, v, v, 1 << 20, None) == -2
+    assert lib.cqr_batched_factor_solve(4, 0, None, v, v, v, v, v, v, v, v, 1 << 20, None) == -3
+    assert lib.cqr_batched_factor_solve(4, 0, v, v, v, None, v, v, v, v, v, 1 << 20, None) == -6
+    assert lib.cqr_batched_factor_solve(4, 0, v, v, v, v, v, v, None, v, v, 1 << 20, None) == -9
+    assert lib.cqr_batched_factor_solve(4, 1, v, v, v, v, v, v, v, v, v, 8, None) == -101
+    from paper_2403_06218_amd import batched
+    insts = batched.instances()
+    assert len(insts) >= 4 and {i["dtype"] for i in insts} == {0, 1}
+    assert all(i["bw"] in (16, 32) and i["nmax"] in (256, 512) for i in insts)
+    for dt in (torch.float64, torch.float32):
+        plan = batched.get_plan(dt)
+        assert plan["hi"][-1] == 512 and plan["hi"] == sorted(plan["hi"])
+        for h, i in zip(plan["hi"], plan["inst"]):
+            assert insts[i]["nmax"] >= h and insts[i]["dtype"] == (0 if dt == torch.float64 else 1)
+    f64_256 = next(i["id"] for i in insts if i["dtype"] == 0 and i["nmax"] == 256)
+    f32_any = next(i["id"] for i in insts if i["dtype"] == 1)
+    with pytest.raises(_native.CqrError):
+        batched.set_plan(torch.float64, [512], [f64_256])       # nmax too small for the bucket
+    with pytest.raises(_native.CqrError):
+        batched.set_plan(torch.float64, [64, 32], [f64_256, f64_256])  # bounds not ascending
+    with pytest.raises(_native.CqrError):
+        batched.set_plan(torch.float64, [64], [f32_any])        # wrong element type
+    old = batched.get_plan(torch.float64)
+    batched.set_plan(torch.float64, [100, 256], [f64_256, f64_256])
+    assert batched.get_plan(torch.float64) == {"hi": [100, 256], "inst": [f64_256, f64_256]}
+    assert batched.block_width(100) == insts[f64_256]["bw"]
+    batched.set_plan(torch.float64, old["hi"], old["inst"])
