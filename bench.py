@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 METRIC = "GFLOP/s at n=32768: BF16-MFMA LU+FP64 IR vs FP64 LUPP, HPL resid<16"
 PEAK_FP64_MFMA_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
 PEAK_HBM_GBS = 8000.0
+PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
 
 
 def parse():
@@ -39,6 +40,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-target-s", type=float, default=15.0, help="target oracle time for the CPU sample")
     p.add_argument("--no-mixed", action="store_true", help="skip the BF16 + FP64-refinement form")
+    p.add_argument("--no-batched", action="store_true", help="skip the batched form (10,000 uneven sizes)")
+    p.add_argument("--no-adjoint", action="store_true", help="skip the adjoint form (256 x n=512)")
+    p.add_argument("--no-tune", action="store_true", help="batched form: keep the library's default plan")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="before the run, copy this many MiB device-to-device once (reference kernel for HBM counters)")
     return p.parse_args()
@@ -110,6 +114,138 @@ def bench_mixed(cqr, torch, n: int, b: int, K: int, W: int, seed: int, fp64_ms: 
             "ir_iterations": [o[1] for o in out], "hpl_scaled_residual": [o[2] for o in out],
             "info": [o[0] for o in out], "dtype": "bf16 mfma (fp32 acc) + f64 panel + f64 refinement",
             "workload": "n=%d, b=%d, off-diagonal U[-0.5,0.5], diagonal = row sum + 1, 1 RHS U[-1,1]" % (n, b)}
+
+
+def _graph_ms(torch, run, reset, K, W):
+    """Captures run() in a hipGraph and times K replays (after W) with HIP events
+    on the current stream; reset() (untimed) restores the inputs before each."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        reset()
+        run()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        run()
+    times = []
+    for i in range(W + K):
+        reset()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        if i >= W:
+            times.append(e0.elapsed_time(e1))
+    return float(np.median(times)), times
+
+
+def bench_batched(torch, K: int, W: int, seed: int, tune: bool) -> dict:
+    """10,000 square systems, n uniform in [8, 256], U[-1, 1) entries, one RHS
+    each, FP64 and FP32: the whole batch (factor + solve) in one hipGraph replay."""
+    from paper_2403_06218_amd import batched, costmodel, inputs
+    sizes = inputs.batch_sizes(10000, 8, 256, seed=seed)
+    out = {"workload": "10000 matrices, n ~ U[8, 256] (integer), U[-1,1) entries, 1 RHS each",
+           "flop_model": "sum over matrices of Table 1 CA3(b_i, n_i, n_i) + 3 n_i^2"}
+    for dt, name, peak in ((torch.float64, "f64", PEAK_FP64_MFMA_TFLOPS), (torch.float32, "f32",
+                                                                           PEAK_FP32_MFMA_TFLOPS)):
+        t0 = time.perf_counter()
+        tuned = batched.tune(dt, buckets=((0, 64), (64, 128), (128, 256), (256, 512)), count=1024) if tune else None
+        tune_s = time.perf_counter() - t0
+        insts = batched.instances()
+        plan = batched.get_plan(dt)
+        batch = batched.PackedBatch(sizes, dtype=dt)
+        batched._fill(batch, seed + 100)
+        a0, b0 = batch.A.clone(), batch.B.clone()
+        work = torch.empty(max(batched.workspace_size(batch.count), 1), dtype=torch.uint8, device="cuda")
+
+        def reset():
+            batch.A.copy_(a0)
+            batch.B.copy_(b0)
+
+        ms, times = _graph_ms(torch, lambda: batched.factor_solve(batch, work), reset, K, W)
+        flops = 0.0
+        uniq, cnt = np.unique(sizes, return_counts=True)
+        for nn, c in zip(uniq, cnt):
+            flops += c * (costmodel.ca3(batched.block_width(int(nn), dt), int(nn), int(nn))
+                          + costmodel.solve_flops(int(nn)))
+        info = batch.info.cpu().numpy()
+        eps = 2.0 ** -52 if dt == torch.float64 else 2.0 ** -23
+        rng = np.random.default_rng(7)
+        worst = 0.0
+        for i in rng.choice(batch.count, 64, replace=False):
+            n = int(sizes[i])
+            o, vo = int(batch.offsets[i]), int(batch.voffsets[i])
+            Y = a0[o:o + n * n].view(n, n).t().double()
+            x = batch.B[vo:vo + n].double()
+            r = (Y @ x - b0[vo:vo + n].double()).abs().max() / (Y.abs().sum(dim=1).max() * x.abs().max() * n * eps)
+            worst = max(worst, float(r))
+        tflops = flops / (ms * 1e-3) / 1e12
+        out[name] = {"ms_per_batch": round(ms, 3), "matrices_per_s": round(batch.count / (ms * 1e-3), 1),
+                     "value": round(tflops * 1e3, 2), "unit": "GFLOP/s", "flops_per_batch": flops,
+                     "roofline": {"bound": "mfma", "achieved": round(tflops, 3), "peak": peak, "unit": "TFLOP/s",
+                                  "frac": round(tflops / peak, 4)},
+                     "plan": {"hi": plan["hi"], "instances": [insts[i] for i in plan["inst"]]},
+                     "tune_s": round(tune_s, 2) if tuned else None,
+                     "tune_ms": tuned["timings_ms"] if tuned else None,
+                     "fallback_matrices": int((info > 0).sum()), "invalid": int((info < 0).sum()),
+                     "hpl_scaled_residual_max_of_64_sampled": worst, "replay_ms": [round(t, 3) for t in times]}
+        del batch, a0, b0
+        torch.cuda.empty_cache()
+    return out
+
+
+def bench_adjoint(torch, K: int, W: int, seed: int) -> dict:
+    """256 systems n = 512 (U[-1, 1) + 4 I, RHS U[-1, 1)), loss = sum(w x):
+    forward (batched factor + solve) and the adjoint kernel, FP64 and FP32."""
+    from paper_2403_06218_amd import batched, costmodel
+    from paper_2403_06218_amd import synth_uniform
+    count, n = 256, 512
+    out = {"workload": "256 matrices n=512, U[-1,1) + 4I, RHS and w U[-1,1), loss = sum(w*x)"}
+    for dt, name in ((torch.float64, "f64"), (torch.float32, "f32")):
+        batch = batched.PackedBatch([n] * count, dtype=dt)
+        tmp = torch.empty(batch.A.numel(), dtype=torch.float64, device="cuda")
+        synth_uniform(tmp.view(-1, 1), seed + 300)
+        A3 = tmp.view(count, n, n)
+        A3.diagonal(dim1=1, dim2=2).add_(4.0)
+        batch.A.copy_(tmp)
+        tb = torch.empty(batch.B.numel(), dtype=torch.float64, device="cuda")
+        synth_uniform(tb.view(-1, 1), seed + 301)
+        batch.B.copy_(tb)
+        synth_uniform(tb.view(-1, 1), seed + 302)
+        g = tb.to(dt)
+        a0, b0 = batch.A.clone(), batch.B.clone()
+        del tmp
+        work = torch.empty(max(batched.workspace_size(count), 1), dtype=torch.uint8, device="cuda")
+
+        def reset():
+            batch.A.copy_(a0)
+            batch.B.copy_(b0)
+
+        fwd_ms, _ = _graph_ms(torch, lambda: batched.factor_solve(batch, work), reset, K, W)
+        reset()
+        batched.factor_solve(batch, work)
+        dA = torch.empty_like(batch.A)
+        db = torch.empty_like(batch.B)
+        bwd_ms, _ = _graph_ms(torch, lambda: batched.solve_backward(batch, g, dA, db), lambda: None, K, W)
+        es = batch.A.element_size()
+        # Algorithmic bytes per matrix: read Q (n^2) and the upper triangle of R
+        # (n(n+1)/2), write dA (n^2); vectors x, g, db (3n).
+        bytes_ = count * es * (2.0 * n * n + n * (n + 1) / 2.0 + 3.0 * n)
+        gbs = bytes_ / (bwd_ms * 1e-3) / 1e9
+        fwd_flops = count * (costmodel.ca3(batched.block_width(n, dt), n, n) + costmodel.solve_flops(n))
+        out[name] = {"forward_ms": round(fwd_ms, 3), "backward_ms": round(bwd_ms, 3),
+                     "forward_gflops": round(fwd_flops / (fwd_ms * 1e-3) / 1e9, 1),
+                     "backward_roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                                           "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                                           "algorithmic_bytes": bytes_},
+                     "info_nonzero": int((batch.info.cpu() != 0).sum())}
+        del batch, a0, b0, dA, db
+        torch.cuda.empty_cache()
+    return out
 
 
 def measured_traffic(role: str):
@@ -237,6 +373,10 @@ def main():
         del Ys
         torch.cuda.empty_cache()
         out["mixed"] = bench_mixed(cqr, torch, n, b, K, W, args.seed, ms_step)
+    if not args.no_batched:
+        out["batched"] = bench_batched(torch, K, W, args.seed, not args.no_tune)
+    if not args.no_adjoint:
+        out["adjoint"] = bench_adjoint(torch, K, W, args.seed)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, b, args.seed, args.cpu_target_s)
     print(json.dumps(out), flush=True)

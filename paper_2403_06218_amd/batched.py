@@ -67,6 +67,11 @@ class PackedBatch:
             self.b_ptrs = (voff * es + self.B.data_ptr()).to(device)
         else:
             self.b_ptrs = None
+        # Byte offsets of every matrix / vector, for building pointer arrays of
+        # other buffers with the same packing on the device (no host copy, so
+        # that calls stay capturable).
+        self.moff_bytes = (off * es).to(device)
+        self.voff_bytes = (torch.from_numpy(self.voffsets[:-1].copy()) * es).to(device)
         self.info = torch.zeros(max(self.count, 1), dtype=torch.int32, device=device)
         self.flags = torch.zeros(max(self.count, 1), dtype=torch.int32, device=device)
 
@@ -233,12 +238,9 @@ def solve_backward(batch: PackedBatch, g: torch.Tensor, dA: torch.Tensor, db: to
         if t.dtype != batch.dtype or not t.is_cuda or t.numel() < ref.numel() or not t.is_contiguous():
             raise ValueError("%s must be a contiguous %s GPU tensor of at least %d elements"
                              % (name, batch.dtype, ref.numel()))
-    es = batch.A.element_size()
-    off_m = torch.from_numpy(batch.offsets[:-1] * es).to(batch.A.device)
-    off_v = torch.from_numpy(batch.voffsets[:-1] * es).to(batch.A.device)
-    g_ptrs = off_v + g.data_ptr()
-    db_ptrs = off_v + db.data_ptr()
-    da_ptrs = off_m + dA.data_ptr()
+    g_ptrs = batch.voff_bytes + g.data_ptr()
+    db_ptrs = batch.voff_bytes + db.data_ptr()
+    da_ptrs = batch.moff_bytes + dA.data_ptr()
     rc = _native.lib().cqr_batched_solve_backward(
         batch.count, _DT[batch.dtype], _vp(batch.n_dev), _vp(batch.a_ptrs), _vp(batch.lda_dev), _vp(batch.r_ptrs),
         _vp(batch.ldr_dev), _vp(batch.b_ptrs), _vp(g_ptrs), _vp(da_ptrs), _vp(batch.lda_dev), _vp(db_ptrs),
