@@ -108,11 +108,24 @@ def bench_mixed(cqr, torch, n: int, b: int, K: int, W: int, seed: int, fp64_ms: 
     cqr.qr_mixed(Y, b, Q=Q, R=R, work=work)
     torch.cuda.synchronize()
     tf = time.perf_counter() - t1
+    # Per-role launch times of one more factorisation (library HIP events).
+    cqr.prof_reset()
+    cqr.prof_enable(True)
+    cqr.qr_mixed(Y, b, Q=Q, R=R, work=work)
+    torch.cuda.synchronize()
+    cqr.prof_enable(False)
+    roles = {}
+    for name in cqr.prof_names():
+        r = cqr.prof_query(name)
+        if r["launches"]:
+            roles[name] = {"ms": round(r["ms"], 3), "launches": r["launches"],
+                           "tflops": round(r["flops"] / (r["ms"] * 1e-3) / 1e12, 2) if r["flops"] else None}
     flops = costmodel.ca3(b, n, n) + costmodel.solve_flops(n)
     return {"value": round(flops / el / 1e9, 2), "unit": "GFLOP/s", "ms_per_step": round(el * 1e3, 2),
             "factor_ms": round(tf * 1e3, 2), "speedup_vs_fp64": round(fp64_ms / (el * 1e3), 3),
             "ir_iterations": [o[1] for o in out], "hpl_scaled_residual": [o[2] for o in out],
             "info": [o[0] for o in out], "dtype": "bf16 mfma (fp32 acc) + f64 panel + f64 refinement",
+            "factor_breakdown": roles,
             "workload": "n=%d, b=%d, off-diagonal U[-0.5,0.5], diagonal = row sum + 1, 1 RHS U[-1,1]" % (n, b)}
 
 

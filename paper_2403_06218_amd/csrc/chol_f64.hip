@@ -6,127 +6,172 @@
 namespace cqr {
 namespace {
 
-// One workgroup of 16 x 16 threads (4 waves, one per SIMD) factors W (b x b,
-// b <= 16 TS) as L L^T and inverts L.  Thread (ty, tx) = (tid / 16, tid % 16)
-// keeps the TS x TS register tile of rows ty*TS.. and columns tx*TS.. .
+typedef double chol_d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ chol_d4 mma64(double a, double b, chol_d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+  return __hiloint2double(hi, lo);
+}
+
+constexpr int kCB = 128;       // largest block width
+constexpr int kCLD = kCB + 1;  // LDS row stride (odd: column walks are conflict-free)
+
+// One workgroup (4 waves) factors W (b x b, b <= 128) as L L^T and inverts L,
+// blocked by panels of 16 columns, with the whole matrix held once in LDS:
+// the lower triangle (with the diagonal) holds L, the strict upper triangle
+// holds X^T for X = L^{-1}, and sD the diagonal of X (1 / L_ii).  Rows and
+// columns b .. 16 ceil(b/16) - 1 are padded with the identity.
 //
-// Factorisation, right-looking, one barrier per column k: the owners of
-// column k publish its current values; every thread then takes the pivot
-// d = W(k,k), forms l = sqrt(d), scales the column by 1/l and applies the
-// rank-1 update to its tile.  A pivot that is not > 0 (NaN included) marks a
-// breakdown; the kernel still runs to the end and reports it in status.
-// L is then parked in LDS and the same registers hold X = L^{-1}, built
-// right-looking from X = I with one barrier per k: row k of X is scaled by
-// 1/L(k,k) and L(i,k) times it is subtracted from every row i > k.
-// Published columns/rows are double-buffered in LDS by the parity of k.
-template <int TS>
+// Panel p (columns c0 = 16p .. c0+15), left-looking:
+//   1. panel update  A[c0:, c0:c0+16] -= L[c0:, :c0] L[c0:c0+16, :c0]^T (MFMA);
+//   2. wave 0 factors the 16 x 16 diagonal block in registers (readlane
+//      broadcasts) and forms its inverse X_pp column by column;
+//   3. the rows below take L = A X_pp^T (MFMA).
+// Then X block row by block row: X_i,0:i = -X_ii (L_i,0:i X_0:i,0:i) (MFMA).
+// A pivot that is not > 0 (NaN included) marks a breakdown; the kernel runs
+// to the end and reports it in status.
 __global__ void __launch_bounds__(256)
 chol_inv_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __restrict__ LT, double* __restrict__ XT,
                 int* status, int code, int blk) {
-  constexpr int TG = 16, NB = TG * TS;
   if (status[0] != 0) return;
-  __shared__ double colbuf[2][NB];
-  __shared__ double rowbuf[2][NB];
-  __shared__ double sL[NB][NB + 1];
+  __shared__ double sA[kCB * kCLD];
+  __shared__ double sD[kCB];
+  __shared__ double sT[16 * kCLD];
   __shared__ int bad;
-  const int tid = threadIdx.x, ty = tid / TG, tx = tid % TG;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int nb = (b + 15) & ~15, P = nb >> 4;
   if (tid == 0) bad = 0;
-  double w[TS][TS];
-#pragma unroll
-  for (int r = 0; r < TS; ++r)
-#pragma unroll
-    for (int c = 0; c < TS; ++c) {
-      const int i = ty * TS + r, j = tx * TS + c;
-      w[r][c] = (i < b && j < b) ? W[i + (int64_t)j * ldw] : (i == j ? 1.0 : 0.0);
-    }
+  for (int e = tid; e < nb * nb; e += 256) {
+    const int j = e / nb, i = e - j * nb;
+    sA[i * kCLD + j] = (i < b && j < b) ? W[i + (int64_t)j * ldw] : (i == j ? 1.0 : 0.0);
+  }
   __syncthreads();
 
-  for (int kb = 0; kb < TG && kb * TS < b; ++kb) {
+  for (int p = 0; p < P; ++p) {
+    const int c0 = 16 * p;
+    if (p > 0) {
+      for (int t = p + wave; t < P; t += 4) {
+        chol_d4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < c0; k0 += 4)
+          acc = mma64(sA[(16 * t + li) * kCLD + k0 + lg], sA[(c0 + li) * kCLD + k0 + lg], acc);
 #pragma unroll
-    for (int kk = 0; kk < TS; ++kk) {
-      const int k = kb * TS + kk;
-      const int buf = k & 1;
-      if (tx == kb) {
-#pragma unroll
-        for (int r = 0; r < TS; ++r) colbuf[buf][ty * TS + r] = w[r][kk];
+        for (int v = 0; v < 4; ++v) sA[(16 * t + lg + 4 * v) * kCLD + c0 + li] -= acc[v];
       }
       __syncthreads();
-      const double d = colbuf[buf][k];
-      if (tid == 0 && k < b && !(d > 0.0)) bad = 1;
-      const double l = sqrt(d);
-      const double rl = 1.0 / l;
-      // Column entries of rows/columns <= k enter the update as exact zeros,
-      // which leaves those tile entries unchanged without per-element branches.
-      double lim[TS], ljm[TS];
+    }
+    if (wave == 0) {
+      // Lane i < 16 holds row i of the diagonal block.
+      double a[16];
 #pragma unroll
-      for (int r = 0; r < TS; ++r) lim[r] = (ty * TS + r > k) ? colbuf[buf][ty * TS + r] * rl : 0.0;
+      for (int j = 0; j < 16; ++j) a[j] = (lane < 16 && j <= lane) ? sA[(c0 + lane) * kCLD + c0 + j] : 0.0;
+      bool ok = true;
+      double dinv = 0.0;
 #pragma unroll
-      for (int c = 0; c < TS; ++c) ljm[c] = (tx * TS + c > k) ? colbuf[buf][tx * TS + c] * rl : 0.0;
-#pragma unroll
-      for (int r = 0; r < TS; ++r)
-#pragma unroll
-        for (int c = 0; c < TS; ++c) w[r][c] -= lim[r] * ljm[c];
-      if (tx == kb) {
-#pragma unroll
-        for (int r = 0; r < TS; ++r) {
-          const int i = ty * TS + r;
-          w[r][kk] = (i > k) ? lim[r] : ((i == k) ? l : w[r][kk]);
+      for (int k = 0; k < 16; ++k) {
+        const double d = readlane_f64(a[k], k);
+        if (!(d > 0.0)) ok = false;
+        const double lkk = sqrt(d);
+        const double inv = 1.0 / lkk;
+        if (lane == k) {
+          a[k] = lkk;
+          dinv = inv;
+        } else if (lane > k) {
+          a[k] *= inv;
         }
+#pragma unroll
+        for (int j = k + 1; j < 16; ++j) {
+          const double ljk = readlane_f64(a[k], j);
+          if (lane >= j) a[j] -= a[k] * ljk;
+        }
+        // Keeps the scheduler from hoisting later steps' broadcasts (scalar
+        // registers) above this step.
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (lane == 0 && !ok) bad = 1;
+      if (lane < 16) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+          if (j <= lane) sA[(c0 + lane) * kCLD + c0 + j] = a[j];
+        sD[c0 + lane] = dinv;
+      }
+      // The wave's LDS writes complete before its lanes read each other's.
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      // Lane j < 16 forms column j of X_pp = L_pp^{-1} and stores it
+      // transposed in the strict upper part of the diagonal block.
+      double x[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < i; ++k) acc += sA[(c0 + i) * kCLD + c0 + k] * x[k];
+        const double di = sD[c0 + i];
+        x[i] = (i == lane) ? di : ((i > lane) ? -di * acc : 0.0);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (lane < 16) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+          if (i > lane) sA[(c0 + lane) * kCLD + c0 + i] = x[i];
       }
     }
+    __syncthreads();
+    for (int t = p + 1 + wave; t < P; t += 4) {
+      chol_d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 16; kk += 4) {
+        const int k = kk + lg;
+        // B(k, j) = X_pp(j, k) with j = li.
+        const double bx = (li > k) ? sA[(c0 + k) * kCLD + c0 + li] : ((li == k) ? sD[c0 + k] : 0.0);
+        acc = mma64(sA[(16 * t + li) * kCLD + c0 + k], bx, acc);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sA[(16 * t + lg + 4 * v) * kCLD + c0 + li] = acc[v];
+    }
+    __syncthreads();
   }
-  // Park L (lower part; zero above) in LDS and write L^T out.
-#pragma unroll
-  for (int r = 0; r < TS; ++r)
-#pragma unroll
-    for (int c = 0; c < TS; ++c) {
-      const int i = ty * TS + r, j = tx * TS + c;
-      const double v = (i >= j) ? w[r][c] : 0.0;
-      sL[i][j] = v;
-      if (i < b && j < b) LT[j + (int64_t)i * b] = v;  // LT(j, i) = L(i, j)
-    }
-  // The same registers now hold X, starting from I.
-#pragma unroll
-  for (int r = 0; r < TS; ++r)
-#pragma unroll
-    for (int c = 0; c < TS; ++c) w[r][c] = (ty * TS + r == tx * TS + c) ? 1.0 : 0.0;
-  __syncthreads();
 
-  for (int kb = 0; kb < TG && kb * TS < b; ++kb) {
-#pragma unroll
-    for (int kk = 0; kk < TS; ++kk) {
-      const int k = kb * TS + kk;
-      const int buf = k & 1;
-      if (ty == kb) {
-#pragma unroll
-        for (int c = 0; c < TS; ++c) rowbuf[buf][tx * TS + c] = w[kk][c];
+  for (int i = 1; i < P; ++i) {
+    const int r0 = 16 * i;
+    // T = L[r0:r0+16, 0:r0] X[0:r0, 0:r0] (X lower: start each tile's sum at its diagonal).
+    for (int jt = wave; jt < i; jt += 4) {
+      chol_d4 acc = {0.0, 0.0, 0.0, 0.0};
+      const int j = 16 * jt + li;
+      for (int k0 = 16 * jt; k0 < r0; k0 += 4) {
+        const int k = k0 + lg;
+        const double bx = (k > j) ? sA[j * kCLD + k] : ((k == j) ? sD[k] : 0.0);
+        acc = mma64(sA[(r0 + li) * kCLD + k], bx, acc);
       }
-      __syncthreads();
-      const double rl = 1.0 / sL[k][k];
-      double xk[TS];
 #pragma unroll
-      for (int c = 0; c < TS; ++c) xk[c] = rowbuf[buf][tx * TS + c] * rl;
-#pragma unroll
-      for (int r = 0; r < TS; ++r) {
-        const int i = ty * TS + r;
-        const double lik = (i > k) ? sL[i][k] : 0.0;
-#pragma unroll
-        for (int c = 0; c < TS; ++c) w[r][c] -= lik * xk[c];
-      }
-      if (ty == kb) {
-#pragma unroll
-        for (int c = 0; c < TS; ++c) w[kk][c] = xk[c];
-      }
+      for (int v = 0; v < 4; ++v) sT[(lg + 4 * v) * kCLD + 16 * jt + li] = acc[v];
     }
+    __syncthreads();
+    // X[r0:r0+16, 0:r0] = -X_ii T, stored transposed above the diagonal.
+    for (int jt = wave; jt < i; jt += 4) {
+      chol_d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 16; kk += 4) {
+        const int k = kk + lg;
+        const double ax = (li > k) ? sA[(r0 + k) * kCLD + r0 + li] : ((li == k) ? sD[r0 + k] : 0.0);
+        acc = mma64(ax, sT[k * kCLD + 16 * jt + li], acc);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sA[(16 * jt + li) * kCLD + r0 + lg + 4 * v] = -acc[v];
+    }
+    __syncthreads();
   }
 
-#pragma unroll
-  for (int r = 0; r < TS; ++r)
-#pragma unroll
-    for (int c = 0; c < TS; ++c) {
-      const int i = ty * TS + r, j = tx * TS + c;
-      if (i < b && j < b) XT[j + (int64_t)i * b] = (i >= j) ? w[r][c] : 0.0;  // XT(j, i) = X(i, j)
-    }
+  // LT(j, i) = L(i, j) and XT(j, i) = X(i, j), both upper triangular, ld b.
+  for (int e = tid; e < b * b; e += 256) {
+    const int i = e / b, j = e - i * b;
+    LT[j + (int64_t)i * b] = (i >= j) ? sA[i * kCLD + j] : 0.0;
+    XT[j + (int64_t)i * b] = (i > j) ? sA[j * kCLD + i] : ((i == j) ? sD[i] : 0.0);
+  }
   __syncthreads();
   if (tid == 0 && bad) {
     status[1] = blk;
@@ -223,14 +268,7 @@ hipError_t chol_inv(int b, const double* W, int64_t ldw, double* LT, double* XT,
   if (b < 1 || b > 128) return hipErrorInvalidValue;
   const double bb = (double)b;
   const int slot = prof_begin(s);
-  if (b <= 16)
-    hipLaunchKernelGGL(chol_inv_kernel<1>, dim3(1), dim3(256), 0, s, b, W, ldw, LT, XT, status, code, blk);
-  else if (b <= 32)
-    hipLaunchKernelGGL(chol_inv_kernel<2>, dim3(1), dim3(256), 0, s, b, W, ldw, LT, XT, status, code, blk);
-  else if (b <= 64)
-    hipLaunchKernelGGL(chol_inv_kernel<4>, dim3(1), dim3(256), 0, s, b, W, ldw, LT, XT, status, code, blk);
-  else
-    hipLaunchKernelGGL(chol_inv_kernel<8>, dim3(1), dim3(256), 0, s, b, W, ldw, LT, XT, status, code, blk);
+  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(256), 0, s, b, W, ldw, LT, XT, status, code, blk);
   hipError_t e = hipGetLastError();
   prof_end(slot, ROLE_CHOL, s, bb * bb * bb / 3.0, 8.0 * 3.0 * bb * bb);
   return e;
