@@ -40,6 +40,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-target-s", type=float, default=15.0, help="target oracle time for the CPU sample")
     p.add_argument("--no-mixed", action="store_true", help="skip the BF16 + FP64-refinement form")
+    p.add_argument("--mixed-b", type=int, default=256, help="block width of the BF16 form")
     p.add_argument("--no-batched", action="store_true", help="skip the batched form (10,000 uneven sizes)")
     p.add_argument("--no-adjoint", action="store_true", help="skip the adjoint form (256 x n=512)")
     p.add_argument("--no-tune", action="store_true", help="batched form: keep the library's default plan")
@@ -385,7 +386,7 @@ def main():
     if not args.no_mixed:
         del Ys
         torch.cuda.empty_cache()
-        out["mixed"] = bench_mixed(cqr, torch, n, b, K, W, args.seed, ms_step)
+        out["mixed"] = bench_mixed(cqr, torch, n, args.mixed_b, K, W, args.seed, ms_step)
     if not args.no_batched:
         out["batched"] = bench_batched(torch, K, W, args.seed, not args.no_tune)
     if not args.no_adjoint:

@@ -126,7 +126,8 @@ int cqr_solve(int64_t n, const double* Q, int64_t ldq, const double* R, int64_t 
  *   Y, ldy   in (device, FP64, 16-byte aligned, even ldy): q x r; not modified.
  *   Q, ldq   out (FP32): q x r with Q^T Q ~ I to BF16 accuracy.
  *   R, ldr   out (FP32): r x r upper triangular.
- *   b        block width: a multiple of 16, at most 128.
+ *   b        block width: a multiple of 16, at most 256 (a width above 128
+ *            factors its Gram matrix as a 2 x 2 block).
  *   info     host, may be NULL: 0, or the 1-based index of the first block whose
  *            Cholesky factorisation broke down; then Q and R are not valid (this
  *            form has no CGS2 fallback; use cqr_factor).

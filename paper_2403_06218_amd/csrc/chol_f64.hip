@@ -37,7 +37,7 @@ constexpr int kCLD = kCB + 1;  // LDS row stride (odd: column walks are conflict
 // to the end and reports it in status.
 __global__ void __launch_bounds__(256)
 chol_inv_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __restrict__ LT, double* __restrict__ XT,
-                int* status, int code, int blk) {
+                int64_t ldo, int* status, int code, int blk) {
   if (status[0] != 0) return;
   __shared__ double sA[kCB * kCLD];
   __shared__ double sD[kCB];
@@ -166,11 +166,11 @@ chol_inv_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __rest
     __syncthreads();
   }
 
-  // LT(j, i) = L(i, j) and XT(j, i) = X(i, j), both upper triangular, ld b.
+  // LT(j, i) = L(i, j) and XT(j, i) = X(i, j), both upper triangular, ld ldo.
   for (int e = tid; e < b * b; e += 256) {
     const int i = e / b, j = e - i * b;
-    LT[j + (int64_t)i * b] = (i >= j) ? sA[i * kCLD + j] : 0.0;
-    XT[j + (int64_t)i * b] = (i > j) ? sA[j * kCLD + i] : ((i == j) ? sD[i] : 0.0);
+    LT[j + (int64_t)i * ldo] = (i >= j) ? sA[i * kCLD + j] : 0.0;
+    XT[j + (int64_t)i * ldo] = (i > j) ? sA[j * kCLD + i] : ((i == j) ? sD[i] : 0.0);
   }
   __syncthreads();
   if (tid == 0 && bad) {
@@ -263,15 +263,59 @@ unsigned grid_for(int64_t total) {
 
 }  // namespace
 
-hipError_t chol_inv(int b, const double* W, int64_t ldw, double* LT, double* XT, int* status, int code, int blk,
-                    hipStream_t s) {
-  if (b < 1 || b > 128) return hipErrorInvalidValue;
+static hipError_t chol_inv_ld(int b, const double* W, int64_t ldw, double* LT, double* XT, int64_t ldo, int* status,
+                       int code, int blk, hipStream_t s) {
+  if (b < 1 || b > kCB) return hipErrorInvalidValue;
   const double bb = (double)b;
   const int slot = prof_begin(s);
-  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(256), 0, s, b, W, ldw, LT, XT, status, code, blk);
+  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(256), 0, s, b, W, ldw, LT, XT, ldo, status, code, blk);
   hipError_t e = hipGetLastError();
   prof_end(slot, ROLE_CHOL, s, bb * bb * bb / 3.0, 8.0 * 3.0 * bb * bb);
   return e;
+}
+
+hipError_t chol_inv(int b, const double* W, int64_t ldw, double* LT, double* XT, int* status, int code, int blk,
+                    hipStream_t s) {
+  return chol_inv_ld(b, W, ldw, LT, XT, b, status, code, blk, s);
+}
+
+// 2 x 2 block form for kCB < b <= 2 kCB, with b1 = kCB and b2 = b - kCB:
+//   L11 L11^T = W11;  U12 = L21^T = X11 W12;  S = W22 - U12^T U12;  L22 L22^T = S;
+//   X21^T = -X11^T U12 X22^T.
+// Writes LT = [L11^T U12; 0 L22^T] and XT = [X11^T X21^T; 0 X22^T] (ld b).
+// W's trailing block is overwritten by S; tmp holds b1 x b2 doubles.
+hipError_t chol_inv_wide(int b, double* W, int64_t ldw, double* LT, double* XT, double* tmp, int* status, int code,
+                         int blk, hipStream_t s) {
+  if (b <= kCB) return chol_inv(b, W, ldw, LT, XT, status, code, blk, s);
+  if (b > 2 * kCB) return hipErrorInvalidValue;
+  const int b1 = kCB, b2 = b - kCB;
+  const double d1 = b1, d2 = b2;
+  hipError_t e;
+  double* W12 = W + (int64_t)b1 * ldw;
+  double* W22 = W12 + b1;
+  double* U12 = LT + (int64_t)b1 * b;   // LT[0:b1, b1:b]
+  double* X12 = XT + (int64_t)b1 * b;   // XT[0:b1, b1:b] = X21^T
+  if ((e = chol_inv_ld(b1, W, ldw, LT, XT, b, status, code, blk, s)) != hipSuccess) return e;
+  // U12 = X11 W12 = (XT11)^T W12.
+  if ((e = gemm_tn(ROLE_CHOL, b1, b2, b1, 1.0, XT, b, W12, ldw, 0.0, U12, b, nullptr, 0, status, s,
+                   d1 * d1 * d2)) != hipSuccess)
+    return e;
+  // S = W22 - U12^T U12 (in place).
+  if ((e = gemm_tn(ROLE_CHOL, b2, b2, b1, -1.0, U12, b, U12, b, 1.0, W22, ldw, nullptr, 0, status, s,
+                   2.0 * d1 * d2 * d2)) != hipSuccess)
+    return e;
+  if ((e = chol_inv_ld(b2, W22, ldw, LT + b1 + (int64_t)b1 * b, XT + b1 + (int64_t)b1 * b, b, status, code, blk,
+                       s)) != hipSuccess)
+    return e;
+  // X21^T = -(XT11 U12) XT22.
+  if ((e = gemm_nn(ROLE_CHOL, b1, b2, b1, 1.0, XT, b, U12, b, 0.0, tmp, b1, status, s, d1 * d1 * d2)) != hipSuccess)
+    return e;
+  if ((e = gemm_nn(ROLE_CHOL, b1, b2, b2, -1.0, tmp, b1, XT + b1 + (int64_t)b1 * b, b, 0.0, X12, b, status, s,
+                   2.0 * d1 * d2 * d2)) != hipSuccess)
+    return e;
+  // Strictly lower blocks of LT and XT.
+  if ((e = zero_matrix(b2, b1, LT + b1, b, s)) != hipSuccess) return e;
+  return zero_matrix(b2, b1, XT + b1, b, s);
 }
 
 hipError_t copy_matrix(int64_t rows, int64_t cols, const double* src, int64_t lds, double* dst, int64_t ldd,

@@ -61,6 +61,11 @@ hipError_t gemm_bf16_tn(Role role, int64_t M, int64_t N, int64_t K, float alpha,
 // pivot that is not > 0 sets status[0] = code, status[1] = blk.
 hipError_t chol_inv(int b, const double* W, int64_t ldw, double* LT, double* XT, int* status, int code, int blk,
                     hipStream_t s);
+// The same for b <= 256 through a 2 x 2 block split at 128 (MFMA GEMMs for the
+// off-diagonal blocks and the Schur complement).  W's trailing block is
+// overwritten; tmp holds 128 x (b - 128) doubles.
+hipError_t chol_inv_wide(int b, double* W, int64_t ldw, double* LT, double* XT, double* tmp, int* status, int code,
+                         int blk, hipStream_t s);
 
 // dst (rows x cols, ldd) = src (rows x cols, lds); gated on *gate == 0 when gate != NULL.
 hipError_t copy_matrix(int64_t rows, int64_t cols, const double* src, int64_t lds, double* dst, int64_t ldd,

@@ -320,8 +320,8 @@ int mixed_block(int64_t q, int64_t w, int64_t s, const double* Yj, int64_t ldy, 
     // S3/S8, S4/S9, S5/S10 in FP64.
     MX_TRY(gemm_tn(ROLE_GRAM, w, w, q, 1.0, X, q, X, q, 0.0, ws.W, w, (double*)ws.part, ws.part_cap / 2, gate, st,
                    (s > 0 ? 2.0 : 1.0) * dw * dw * dq));
-    MX_TRY(chol_inv((int)w, ws.W, w, pass == 0 ? ws.LT1 : ws.LT2, pass == 0 ? ws.XT1 : ws.XT2, ws.status, pass + 1,
-                    blk, st));
+    MX_TRY(chol_inv_wide((int)w, ws.W, w, pass == 0 ? ws.LT1 : ws.LT2, pass == 0 ? ws.XT1 : ws.XT2, ws.Rjj, ws.status,
+                         pass + 1, blk, st));
     MX_TRY(gemm_nn(ROLE_TRSM, q, w, w, 1.0, X, q, pass == 0 ? ws.XT1 : ws.XT2, w, 0.0, pass == 0 ? ws.T : ws.Qj, q,
                    gate, st, dw * dw * dq));
   }
@@ -354,7 +354,7 @@ int cqr_workspace_size_mixed(int64_t q, int64_t r, int64_t b, int prec, size_t* 
   if (q < 0) return -1;
   if (r < 0 || r > q) return -2;
   if (b < 1) return -3;
-  if (b > 128 || b % 16 != 0) return CQR_ERR_UNSUPPORTED;
+  if (b > 256 || b % 16 != 0) return CQR_ERR_UNSUPPORTED;
   if (prec != CQR_PREC_BF16) return CQR_ERR_UNSUPPORTED;
   if (!bytes) return -5;
   *bytes = mixed_layout(q, r, b, nullptr, nullptr);
@@ -366,7 +366,7 @@ int cqr_factor_mixed(int64_t q, int64_t r, int64_t b, int prec, const double* Y,
   if (q < 0) return -1;
   if (r < 0 || r > q) return -2;
   if (b < 1) return -3;
-  if (b > 128 || b % 16 != 0) return CQR_ERR_UNSUPPORTED;
+  if (b > 256 || b % 16 != 0) return CQR_ERR_UNSUPPORTED;
   if (prec != CQR_PREC_BF16) return CQR_ERR_UNSUPPORTED;
   if (!Y && q * r > 0) return -5;
   if (ldy < (q > 1 ? q : 1) || (ldy & 1)) return ldy < q ? -6 : CQR_ERR_UNSUPPORTED;

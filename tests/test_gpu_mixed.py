@@ -30,7 +30,8 @@ def _host32(T):
     return np.asfortranarray(T.t().cpu().numpy().T).astype(np.float64)
 
 
-@pytest.mark.parametrize("n,b", [(512, 64), (512, 128), (1000, 64), (2048, 128)])
+@pytest.mark.parametrize("n,b", [(512, 64), (512, 128), (1000, 64), (2048, 128), (1024, 256), (1000, 256),
+                                 (700, 256), (600, 144)])
 def test_mixed_factor_against_oracle(n, b):
     """Diagonally dominant input (off-diagonal U[-0.5, 0.5], diagonal = row sum + 1)."""
     Y = inputs.diag_dominant(n, seed=n)
@@ -53,7 +54,7 @@ def test_mixed_factor_against_oracle(n, b):
     assert np.abs(Qh.T @ Qh - np.eye(n)).max() < bound
 
 
-@pytest.mark.parametrize("n,b", [(512, 64), (2048, 128), (4096, 128)])
+@pytest.mark.parametrize("n,b", [(512, 64), (2048, 128), (4096, 128), (4096, 256)])
 def test_mixed_ir_solve_reaches_fp64_residual(n, b):
     Y = inputs.diag_dominant(n, seed=7 + n)
     rhs = inputs.uniform_vector(n, seed=8 + n)
@@ -89,3 +90,5 @@ def test_mixed_rejects_unsupported_block():
     Y = to_dev(inputs.diag_dominant(64, seed=1))
     with pytest.raises(cqr.CqrError):
         cqr.qr_mixed(Y, 100)
+    with pytest.raises(cqr.CqrError):
+        cqr.qr_mixed(to_dev(inputs.diag_dominant(512, seed=1)), 272)
