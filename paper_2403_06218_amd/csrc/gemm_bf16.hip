@@ -9,7 +9,9 @@
 // multiple of 64 with zeros, aligns every column to 16 bytes and gives the
 // leading dimensions in multiples of 8 elements.
 //
-// Tiling: an MT x NT tile per workgroup of WM x WN wave64s; K is walked in
+// Tiling: an MT x NT tile per workgroup of WM x WN wave64s (128 x 256 with
+// 2 x 4 waves when N > 128, so that a row panel of A is streamed once for the
+// whole width; 128 x 128 with 2 x 4 waves; 64-wide tiles with 2 x 2); K is walked in
 // 64-deep stages copied global -> LDS by the LDS-DMA load
 // (global_load_lds_dwordx4, 16 bytes = 8 BF16 per lane) into an S-slot ring
 // with one barrier per stage.  In LDS a column of a stage is 8 chunks of 8
@@ -216,9 +218,10 @@ template <int ROLE, int OUT, int MT, int NT>
 hipError_t launch_bf16(int64_t M, int64_t N, int64_t K, float alpha, const __bf16* A, int64_t lda, const __bf16* B,
                        int64_t ldb, float beta, void* C, int64_t ldc, int64_t kchunk, int nsplit, float* part,
                        const int* gate, hipStream_t s) {
-  constexpr int WM = (MT == 128 && NT == 128) ? 2 : 2;
-  constexpr int WN = (MT == 128 && NT == 128) ? 4 : 2;
-  constexpr int OCC = (MT == 128 && NT == 128) ? 1 : 2;
+  constexpr bool big = MT == 128 && NT >= 128;
+  constexpr int WM = 2;
+  constexpr int WN = big ? 4 : 2;
+  constexpr int OCC = big ? 1 : 2;
   const dim3 grid((unsigned)((M + MT - 1) / MT), (unsigned)((N + NT - 1) / NT), (unsigned)nsplit);
   hipLaunchKernelGGL((gemm_bf16_kernel<ROLE, OUT, MT, NT, 3, WM, WN, OCC>), grid, dim3(64 * WM * WN), 0, s, M, N, K,
                      alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, gate);
@@ -229,6 +232,9 @@ template <int ROLE, int OUT>
 hipError_t launch_bf16_tile(int64_t M, int64_t N, int64_t K, float alpha, const __bf16* A, int64_t lda,
                             const __bf16* B, int64_t ldb, float beta, void* C, int64_t ldc, int64_t kchunk, int nsplit,
                             float* part, const int* gate, hipStream_t s) {
+  if (M > 64 && N > 128)
+    return launch_bf16<ROLE, OUT, 128, 256>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, nsplit, part, gate,
+                                            s);
   if (M > 64 && N > 64)
     return launch_bf16<ROLE, OUT, 128, 128>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, nsplit, part, gate,
                                             s);
@@ -242,7 +248,7 @@ hipError_t launch_bf16_tile(int64_t M, int64_t N, int64_t K, float alpha, const 
 }
 
 int64_t bf16_tiles(int64_t M, int64_t N) {
-  const int64_t mt = M > 64 ? 128 : 64, nt = N > 64 ? 128 : 64;
+  const int64_t mt = M > 64 ? 128 : 64, nt = (M > 64 && N > 128) ? 256 : (N > 64 ? 128 : 64);
   return ((M + mt - 1) / mt) * ((N + nt - 1) / nt);
 }
 
