@@ -28,6 +28,7 @@
 #include <mutex>
 
 #include "internal.h"
+#include "wave_chol.h"
 #include "../../include/cqr.h"
 
 namespace cqr {
@@ -95,9 +96,10 @@ struct BatchArgs {
   int bw;                 // block width, 16 or 32 (<= BW)
 };
 
-// Cholesky W = L L^T of the leading wp x wp part of sW (row-major, ld BW+1),
-// by wave 0: lane i holds row i.  Writes L (row-major, ld BW+1, zero above the
-// diagonal) and 1/L_kk.  Returns false on a pivot that is not > 0 (NaN too).
+// Cholesky W = L L^T of the leading WP x WP part of sW (row-major, ld BW+1),
+// by wave 0 (lane i holds row i; see wave_chol).  Writes L (row-major, ld
+// BW+1, zero above the diagonal) and 1/L_kk.  Returns false on a pivot that is
+// not > 0 (NaN too).
 template <typename T, int WP, int BW>
 __device__ bool chol_wave(const T* sW, T* sL, T* sDinv, int lane) {
   constexpr int LDW = BW + 1;
@@ -105,33 +107,12 @@ __device__ bool chol_wave(const T* sW, T* sL, T* sDinv, int lane) {
   const bool own = lane < WP;
 #pragma unroll
   for (int j = 0; j < WP; ++j) a[j] = own ? sW[lane * LDW + j] : T(0);
-  bool ok = true;
-#pragma unroll
-  for (int k = 0; k < WP; ++k) {
-    if (ok) {
-      const T d = Mf<T>::rl(a[k], k);
-      if (!(d > T(0))) {
-        ok = false;
-      } else {
-        const T lkk = sqrt(d);
-        const T inv = T(1) / lkk;
-        if (lane == k) {
-          a[k] = lkk;
-          sDinv[k] = inv;
-        } else if (lane > k) {
-          a[k] *= inv;
-        }
-#pragma unroll
-        for (int j = k + 1; j < WP; ++j) {
-          const T ljk = Mf<T>::rl(a[k], j);
-          if (lane >= j) a[j] -= a[k] * ljk;
-        }
-      }
-    }
-  }
+  T lii, linv;
+  const bool ok = wave_chol<T, WP>(a, lii, linv, lane);
   if (own) {
 #pragma unroll
-    for (int j = 0; j < WP; ++j) sL[lane * LDW + j] = (j <= lane) ? a[j] : T(0);
+    for (int j = 0; j < WP; ++j) sL[lane * LDW + j] = (j < lane) ? a[j] : ((j == lane) ? lii : T(0));
+    sDinv[lane] = linv;
   }
   return ok;
 }

@@ -2,6 +2,7 @@
 // its factor (Table 1 POTRF, run on the GPU instead of the host), block
 // copies, and the two kernels of the triangular solve.
 #include "internal.h"
+#include "wave_chol.h"
 
 namespace cqr {
 namespace {
@@ -10,12 +11,6 @@ typedef double chol_d4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ chol_d4 mma64(double a, double b, chol_d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
-__device__ __forceinline__ double readlane_f64(double x, int l) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
-  return __hiloint2double(hi, lo);
 }
 
 constexpr int kCB = 128;       // largest block width
@@ -47,9 +42,21 @@ chol_inv_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __rest
   const int li = lane & 15, lg = lane >> 4;
   const int nb = (b + 15) & ~15, P = nb >> 4;
   if (tid == 0) bad = 0;
-  for (int e = tid; e < nb * nb; e += 256) {
-    const int j = e / nb, i = e - j * nb;
-    sA[i * kCLD + j] = (i < b && j < b) ? W[i + (int64_t)j * ldw] : (i == j ? 1.0 : 0.0);
+  // Loads in batches of 16 per thread, so that their latencies overlap.
+  for (int e0 = tid; e0 < nb * nb; e0 += 256 * 16) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = e0 + 256 * u;
+      const int j = e / nb, i = e - j * nb;
+      v[u] = (e < nb * nb && i < b && j < b) ? W[i + (int64_t)j * ldw] : (i == j ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = e0 + 256 * u;
+      const int j = e / nb, i = e - j * nb;
+      if (e < nb * nb) sA[i * kCLD + j] = v[u];
+    }
   }
   __syncthreads();
 
@@ -70,54 +77,42 @@ chol_inv_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __rest
       double a[16];
 #pragma unroll
       for (int j = 0; j < 16; ++j) a[j] = (lane < 16 && j <= lane) ? sA[(c0 + lane) * kCLD + c0 + j] : 0.0;
-      bool ok = true;
-      double dinv = 0.0;
-#pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const double d = readlane_f64(a[k], k);
-        if (!(d > 0.0)) ok = false;
-        const double lkk = sqrt(d);
-        const double inv = 1.0 / lkk;
-        if (lane == k) {
-          a[k] = lkk;
-          dinv = inv;
-        } else if (lane > k) {
-          a[k] *= inv;
-        }
-#pragma unroll
-        for (int j = k + 1; j < 16; ++j) {
-          const double ljk = readlane_f64(a[k], j);
-          if (lane >= j) a[j] -= a[k] * ljk;
-        }
-        // Keeps the scheduler from hoisting later steps' broadcasts (scalar
-        // registers) above this step.
-        __builtin_amdgcn_sched_barrier(0);
-      }
+      double lii, linv;
+      const bool ok = wave_chol<double, 16>(a, lii, linv, lane);
       if (lane == 0 && !ok) bad = 1;
       if (lane < 16) {
 #pragma unroll
-        for (int j = 0; j < 16; ++j)
-          if (j <= lane) sA[(c0 + lane) * kCLD + c0 + j] = a[j];
-        sD[c0 + lane] = dinv;
+        for (int j = 0; j < 16; ++j) {
+          if (j < lane) {
+            sA[(c0 + lane) * kCLD + c0 + j] = a[j];
+            sT[lane * kCLD + j] = a[j] * linv;  // M(i, j) = L(i, j) / L(i, i)
+          }
+        }
+        sA[(c0 + lane) * kCLD + c0 + lane] = lii;
+        sD[c0 + lane] = linv;
       }
       // The wave's LDS writes complete before its lanes read each other's.
       asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-      // Lane j < 16 forms column j of X_pp = L_pp^{-1} and stores it
-      // transposed in the strict upper part of the diagonal block.
+      // Lane j < 16 forms column j of X_pp = L_pp^{-1}: with M = D^{-1} L
+      // (row i scaled by 1 / L_ii, unit diagonal), X = M^{-1} D^{-1} and
+      // column j of M^{-1} is v_j = 1, v_i = -sum_{j <= k < i} M_ik v_k.
+      // Two partial sums halve the dependent chain.
       double x[16];
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
-        double acc = 0.0;
+        double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-        for (int k = 0; k < i; ++k) acc += sA[(c0 + i) * kCLD + c0 + k] * x[k];
-        const double di = sD[c0 + i];
-        x[i] = (i == lane) ? di : ((i > lane) ? -di * acc : 0.0);
-        __builtin_amdgcn_sched_barrier(0);
+        for (int k = 0; k < i; k += 2) {
+          s0 += sT[i * kCLD + k] * x[k];
+          if (k + 1 < i) s1 += sT[i * kCLD + k + 1] * x[k + 1];
+        }
+        x[i] = (i == lane) ? 1.0 : ((i > lane) ? -(s0 + s1) : 0.0);
       }
       if (lane < 16) {
+        const double dj = linv;  // column j of X = (column j of M^{-1}) / L_jj
 #pragma unroll
         for (int i = 0; i < 16; ++i)
-          if (i > lane) sA[(c0 + lane) * kCLD + c0 + i] = x[i];
+          if (i > lane) sA[(c0 + lane) * kCLD + c0 + i] = x[i] * dj;
       }
     }
     __syncthreads();
