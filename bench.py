@@ -44,6 +44,7 @@ def parse():
     p.add_argument("--no-batched", action="store_true", help="skip the batched form (10,000 uneven sizes)")
     p.add_argument("--no-adjoint", action="store_true", help="skip the adjoint form (256 x n=512)")
     p.add_argument("--no-tune", action="store_true", help="batched form: keep the library's default plan")
+    p.add_argument("--no-tall", action="store_true", help="skip the paper's tall-skinny shape (q up to 1e6, r=64, b=16)")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="before the run, copy this many MiB device-to-device once (reference kernel for HBM counters)")
     return p.parse_args()
@@ -262,6 +263,52 @@ def bench_adjoint(torch, K: int, W: int, seed: int) -> dict:
     return out
 
 
+def bench_tall(cqr, torch, K: int, W: int, seed: int) -> dict:
+    """The paper's orthogonalisation shape inside LancSVD (Sec. 4, dense
+    experiments: b = 16, r = 64): CGS-QR of Y in R^{q x 64}, N(0, 1) entries,
+    q in {1e5, 2.5e5, 7.5e5, 1e6}.  HBM-bound; algorithmic bytes
+    8 q (5 b + sum_{j=2..4} (4 s_j + 9 b)) with s_j = 16 (j - 1)."""
+    from paper_2403_06218_amd import costmodel, inputs
+    r, b = 64, 16
+    out = {"workload": "CGS-QR of q x 64, b=16, N(0,1) entries (Box-Muller on the counter stream)"}
+    for q in (100000, 250000, 750000, 1000000):
+        Y0 = torch.from_numpy(np.ascontiguousarray(inputs.normal_matrix(q, r, seed + q).T)).cuda().t()
+        Ys = [Y0.t().contiguous().t() for _ in range(K + W)]
+        R = cqr.colmajor(r, r)
+        work = torch.empty(cqr.workspace_size(q, r, b), dtype=torch.uint8, device="cuda")
+        for i in range(W):
+            cqr.qr(Ys[i], b, R=R, work=work)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = [cqr.qr(Ys[W + i], b, R=R, work=work)[2] for i in range(K)]
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / K * 1e3
+        Yp = Ys[0]
+        Yp.copy_(Y0)
+        cqr.prof_reset()
+        cqr.prof_enable(True)
+        cqr.qr(Yp, b, R=R, work=work)
+        torch.cuda.synchronize()
+        cqr.prof_enable(False)
+        roles = {}
+        for name in cqr.prof_names():
+            rr = cqr.prof_query(name)
+            if rr["launches"]:
+                roles[name] = {"ms": round(rr["ms"], 4), "launches": rr["launches"]}
+        alg_bytes = 8.0 * q * (5 * b + sum(4 * 16 * (j - 1) + 9 * b for j in range(2, 5)))
+        gbs = alg_bytes / (ms * 1e-3) / 1e9
+        Q = Ys[-1]
+        cols = torch.tensor([0, 17, 40, 63], device="cuda")
+        qc = Q[:, cols]
+        orth = float((qc.t() @ qc - torch.eye(4, device="cuda", dtype=torch.float64)).abs().max())
+        out["q=%d" % q] = {"ms": round(ms, 3), "GB_per_s": round(gbs, 1), "frac_hbm": round(gbs / PEAK_HBM_GBS, 4),
+                           "gflops": round(costmodel.ca3(b, q, r) / (ms * 1e-3) / 1e9, 1), "info": infos,
+                           "max_offdiag_QtQ_4_cols": orth, "breakdown": roles}
+        del Ys, Y0, Q
+        torch.cuda.empty_cache()
+    return out
+
+
 def measured_traffic(role: str):
     """HBM bytes per launch of `role` from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary, or None if the GEMM source changed since it was taken."""
@@ -391,6 +438,8 @@ def main():
         out["batched"] = bench_batched(torch, K, W, args.seed, not args.no_tune)
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint(torch, K, W, args.seed)
+    if not args.no_tall:
+        out["tall_skinny"] = bench_tall(cqr, torch, K, W, args.seed)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, b, args.seed, args.cpu_target_s)
     print(json.dumps(out), flush=True)

@@ -196,6 +196,182 @@ gemm_bf16_kernel(int64_t M, int64_t N, int64_t K, float alpha, const __bf16* __r
     }
 }
 
+// 128 x 256 tile with 2 x 4 waves (64 x 64 per wave) and the loads split by
+// wave: waves 0-3 copy A (the row panel, unique to the workgroup and streamed
+// from HBM) into a 6-slot ring, waves 4-7 copy B (shared by all workgroups,
+// served by L2) into a 2-slot ring.  Each wave's vmcnt then counts only its
+// own operand, so A keeps 5 stages (80 KiB) in flight while B is waited for
+// one stage ahead; the two rings fill the 160 KiB of LDS.
+template <int ROLE, int OUT>
+__global__ void __launch_bounds__(512, 1)
+gemm_bf16_wide_kernel(int64_t M, int64_t N, int64_t K, float alpha, const __bf16* __restrict__ A, int64_t lda,
+                      const __bf16* __restrict__ B, int64_t ldb, float beta, void* C, int64_t ldc, int64_t kchunk,
+                      float* __restrict__ part, const int* __restrict__ gate) {
+  if (gate != nullptr && *gate != 0) return;
+  constexpr int MT = 128, NT = 256, WM = 2;
+  constexpr int WTM = 64, WTN = 64, SM = 4, SN = 4;
+  constexpr int SA = 6, SB = 2;
+  constexpr int ASTAGE = MT * kBKT * 2, BSTAGE = NT * kBKT * 2;
+  constexpr int AINS = ASTAGE / 1024 / 4, BINS = BSTAGE / 1024 / 4;  // DMA instructions per loading wave
+  __shared__ __attribute__((aligned(16))) char sA0[ASTAGE], sA1[ASTAGE], sA2[ASTAGE], sA3[ASTAGE], sA4[ASTAGE],
+      sA5[ASTAGE];
+  __shared__ __attribute__((aligned(16))) char sB0[BSTAGE], sB1[BSTAGE];
+  auto slotA = [&](auto c) -> char* {
+    if constexpr (c.value == 0) return sA0;
+    else if constexpr (c.value == 1) return sA1;
+    else if constexpr (c.value == 2) return sA2;
+    else if constexpr (c.value == 3) return sA3;
+    else if constexpr (c.value == 4) return sA4;
+    else return sA5;
+  };
+  auto slotB = [&](auto c) -> char* {
+    if constexpr (c.value == 0) return sB0;
+    else return sB1;
+  };
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const bool aloader = wave < 4;
+  const int lw = aloader ? wave : wave - 4;  // index among the loading waves of its operand
+  const int wm = wave % WM, wn = wave / WM;
+  const int li = lane & 15, lg = lane >> 4;
+  const int64_t m0 = (int64_t)blockIdx.x * MT;
+  const int64_t n0 = (int64_t)blockIdx.y * NT;
+  const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+  const int64_t kend = (K < kbeg + kchunk) ? K : kbeg + kchunk;
+  const int nst = (kend > kbeg) ? (int)((kend - kbeg) / kBKT) : 0;
+
+  // Source offsets of this lane's chunks (clamped past the matrix edge).
+  constexpr int INS = AINS > BINS ? AINS : BINS;
+  int64_t off[INS];
+#pragma unroll
+  for (int t = 0; t < INS; ++t) {
+    const int p = (lw * (aloader ? AINS : BINS) + t) * 64 + lane;
+    const int x = p / 8, c = (p % 8) ^ ((x >> 1) & 7);
+    if (aloader) {
+      const int64_t m = (m0 + x < M) ? m0 + x : M - 1;
+      off[t] = 8 * c + m * lda;
+    } else {
+      const int64_t n = (n0 + x < N) ? n0 + x : N - 1;
+      off[t] = 8 * c + n * ldb;
+    }
+  }
+  auto issueA = [&](int st, auto slot) {
+    const int64_t k0 = kbeg + (int64_t)st * kBKT;
+    char* la = slotA(slot);
+#pragma unroll
+    for (int t = 0; t < AINS; ++t) dma16(A + k0 + off[t], la + (lw * AINS + t) * 1024);
+  };
+  auto issueB = [&](int st, auto slot) {
+    const int64_t k0 = kbeg + (int64_t)st * kBKT;
+    char* lb = slotB(slot);
+#pragma unroll
+    for (int t = 0; t < BINS; ++t) dma16(B + k0 + off[t], lb + (lw * BINS + t) * 1024);
+  };
+
+  f4 acc[SM][SN];
+#pragma unroll
+  for (int i = 0; i < SM; ++i)
+#pragma unroll
+    for (int j = 0; j < SN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  auto compute = [&](auto sa, auto sb) {
+    const char* cA = slotA(sa);
+    const char* cB = slotB(sb);
+#pragma unroll
+    for (int h = 0; h < kBKT / 32; ++h) {
+      const int c = 4 * h + lg;
+      bf16x8 af[SM], bf[SN];
+#pragma unroll
+      for (int i = 0; i < SM; ++i) af[i] = *(const bf16x8*)(cA + chunk_off(c, wm * WTM + i * 16 + li));
+#pragma unroll
+      for (int j = 0; j < SN; ++j) bf[j] = *(const bf16x8*)(cB + chunk_off(c, wn * WTN + j * 16 + li));
+#pragma unroll
+      for (int i = 0; i < SM; ++i)
+#pragma unroll
+        for (int j = 0; j < SN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+  };
+
+  // Step st: wait for stage st of this wave's operand, barrier, refill the
+  // slots freed by step st-1, compute stage st.
+  auto step = [&](int st, auto ca, auto na, auto cb, auto nb) {
+    if (aloader) {
+      if (st + SA - 2 < nst) wait_vmcnt<(SA - 2) * AINS>();
+      else wait_vmcnt<0>();
+    } else {
+      wait_vmcnt<0>();
+    }
+    __syncthreads();
+    if (aloader) {
+      if (st + SA - 1 < nst) issueA(st + SA - 1, na);
+    } else {
+      if (st + SB - 1 < nst) issueB(st + SB - 1, nb);
+    }
+    compute(ca, cb);
+  };
+  using std::integral_constant;
+  if (aloader) {
+    if (nst > 0) issueA(0, integral_constant<int, 0>{});
+    if (nst > 1) issueA(1, integral_constant<int, 1>{});
+    if (nst > 2) issueA(2, integral_constant<int, 2>{});
+    if (nst > 3) issueA(3, integral_constant<int, 3>{});
+    if (nst > 4) issueA(4, integral_constant<int, 4>{});
+  } else {
+    if (nst > 0) issueB(0, integral_constant<int, 0>{});
+  }
+  for (int st = 0; st < nst; st += 6) {
+    step(st, integral_constant<int, 0>{}, integral_constant<int, 5>{}, integral_constant<int, 0>{},
+         integral_constant<int, 1>{});
+    if (st + 1 < nst)
+      step(st + 1, integral_constant<int, 1>{}, integral_constant<int, 0>{}, integral_constant<int, 1>{},
+           integral_constant<int, 0>{});
+    if (st + 2 < nst)
+      step(st + 2, integral_constant<int, 2>{}, integral_constant<int, 1>{}, integral_constant<int, 0>{},
+           integral_constant<int, 1>{});
+    if (st + 3 < nst)
+      step(st + 3, integral_constant<int, 3>{}, integral_constant<int, 2>{}, integral_constant<int, 1>{},
+           integral_constant<int, 0>{});
+    if (st + 4 < nst)
+      step(st + 4, integral_constant<int, 4>{}, integral_constant<int, 3>{}, integral_constant<int, 0>{},
+           integral_constant<int, 1>{});
+    if (st + 5 < nst)
+      step(st + 5, integral_constant<int, 5>{}, integral_constant<int, 4>{}, integral_constant<int, 1>{},
+           integral_constant<int, 0>{});
+  }
+
+  const int64_t zoff = (int64_t)blockIdx.z * M * N;
+#pragma unroll
+  for (int i = 0; i < SM; ++i)
+#pragma unroll
+    for (int j = 0; j < SN; ++j) {
+      const int64_t n = n0 + wn * WTN + j * 16 + li;
+      const int64_t mb = m0 + wm * WTM + i * 16 + 4 * lg;
+      if (n >= N) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t m = mb + v;
+        if (m >= M) continue;
+        const float val = acc[i][j][v];
+        if constexpr (OUT == 0) {
+          part[zoff + m + n * M] = val;
+        } else if constexpr (OUT == 1) {
+          float* Cf = (float*)C;
+          float c = alpha * val;
+          if (beta != 0.f) c += beta * Cf[m + n * ldc];
+          Cf[m + n * ldc] = c;
+        } else {
+          double* Cd = (double*)C;
+          double c = (double)alpha * (double)val;
+          if (beta != 0.f) c += (double)beta * Cd[m + n * ldc];
+          Cd[m + n * ldc] = c;
+        }
+      }
+    }
+}
+
 // C (FP32 or FP64) = alpha * sum_z part[z] + beta * C, in split order.
 template <typename TC>
 __global__ void __launch_bounds__(256)
@@ -232,9 +408,12 @@ template <int ROLE, int OUT>
 hipError_t launch_bf16_tile(int64_t M, int64_t N, int64_t K, float alpha, const __bf16* A, int64_t lda,
                             const __bf16* B, int64_t ldb, float beta, void* C, int64_t ldc, int64_t kchunk, int nsplit,
                             float* part, const int* gate, hipStream_t s) {
-  if (M > 64 && N > 128)
-    return launch_bf16<ROLE, OUT, 128, 256>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, nsplit, part, gate,
-                                            s);
+  if (M > 64 && N > 128) {
+    const dim3 grid((unsigned)((M + 127) / 128), (unsigned)((N + 255) / 256), (unsigned)nsplit);
+    hipLaunchKernelGGL((gemm_bf16_wide_kernel<ROLE, OUT>), grid, dim3(512), 0, s, M, N, K, alpha, A, lda, B, ldb,
+                       beta, C, ldc, kchunk, part, gate);
+    return hipGetLastError();
+  }
   if (M > 64 && N > 64)
     return launch_bf16<ROLE, OUT, 128, 128>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, nsplit, part, gate,
                                             s);

@@ -387,20 +387,43 @@ gemm_dma_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __r
     }
 }
 
-// C = alpha * sum_z part[z] + beta * C, summed in split order (deterministic).
+// C = alpha * sum_z part[z] + beta * C, deterministic: a workgroup covers 64
+// consecutive outputs with 4 groups of 64 threads; group g sums its quarter of
+// the splits in split order (16 loads in flight), and the 4 group sums are
+// added in group order.
 __global__ void __launch_bounds__(256)
 splitk_reduce_kernel(int64_t M, int64_t N, int nsplit, const double* __restrict__ part, double alpha, double beta,
                      double* C, int64_t ldc, const int* __restrict__ gate) {
   if (gate != nullptr && *gate != 0) return;
+  __shared__ double red[4][64];
   const int64_t total = M * N;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
+  const int t = threadIdx.x, o = t & 63, g = t >> 6;
+  const int zper = (nsplit + 3) / 4;
+  const int z0 = g * zper, z1 = (z0 + zper < nsplit) ? z0 + zper : nsplit;
+  for (int64_t base = (int64_t)blockIdx.x * 64; base < total; base += (int64_t)gridDim.x * 64) {
+    const int64_t idx = base + o;
     double s = 0.0;
-    for (int z = 0; z < nsplit; ++z) s += part[(int64_t)z * total + idx];
-    const int64_t m = idx % M, n = idx / M;
-    double c = alpha * s;
-    if (beta != 0.0) c += beta * C[m + n * ldc];
-    C[m + n * ldc] = c;
+    if (idx < total) {
+      int z = z0;
+      for (; z + 16 <= z1; z += 16) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = part[(int64_t)(z + u) * total + idx];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) s += v[u];
+      }
+      for (; z < z1; ++z) s += part[(int64_t)z * total + idx];
+    }
+    red[g][o] = s;
+    __syncthreads();
+    if (g == 0 && idx < total) {
+      const double sum = ((red[0][o] + red[1][o]) + red[2][o]) + red[3][o];
+      const int64_t m = idx % M, n = idx / M;
+      double c = alpha * sum;
+      if (beta != 0.0) c += beta * C[m + n * ldc];
+      C[m + n * ldc] = c;
+    }
+    __syncthreads();
   }
 }
 
@@ -449,6 +472,32 @@ Plan plan_gemm(bool ta, int64_t M, int64_t N, int64_t K, const double* A, int64_
   p.dma = dma_eligible(ta, M, K, A, lda, B, ldb);
   const int kt = p.dma ? kDmaKT : kKT;
   p.nsplit = 1;
+  p.mt = p.nt = 0;
+  // Skinny shapes (block widths up to 32, as in the tall orthogonalisation):
+  // exact-width tiles, and for A^T B enough splits of the long reduction for
+  // about 2048 workgroups.
+  if (p.dma) {
+    if (ta && N <= 16 && M <= 64) { p.mt = 16; p.nt = 16; }
+    else if (ta && M <= 32 && N <= 32) { p.mt = 32; p.nt = 32; }
+    else if (!ta && N <= 16 && M > 64) { p.mt = 128; p.nt = 16; }
+  }
+  if (p.mt != 0) {
+    if (allow_split && ta) {
+      int64_t sp = 2048 / tiles_for(M, N, p.mt, p.nt);
+      const int64_t by_k = K / (8 * kt);
+      const int64_t by_cap = (int64_t)(part_cap / (size_t)(M * N));
+      if (sp > by_k) sp = by_k;
+      if (sp > by_cap) sp = by_cap;
+      p.nsplit = sp > 1 ? (int)sp : 1;
+    }
+    p.kchunk = K > 0 ? K : 1;
+    if (p.nsplit > 1) {
+      p.kchunk = (K + p.nsplit - 1) / p.nsplit;
+      p.kchunk = (p.kchunk + kt - 1) / kt * kt;
+      p.nsplit = (int)((K + p.kchunk - 1) / p.kchunk);
+    }
+    return p;
+  }
   if (allow_split && ta) {
     // Split the reduction so that the workgroups fill whole rounds of the
     // 512 resident slots (two per CU) as closely as possible, each split
@@ -515,6 +564,18 @@ hipError_t launch(const Plan& p, int64_t M, int64_t N, int64_t K, double alpha, 
                   const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double* part, const int* gate,
                   hipStream_t s) {
   if (p.dma) {
+    if (p.mt == 16) {
+      if constexpr (TA)
+        return launch_dma<ROLE, TA, 16, 16, 3, 8, 1, 1>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
+    }
+    if (p.mt == 32) {
+      if constexpr (TA)
+        return launch_dma<ROLE, TA, 32, 32, 3, 4>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
+    }
+    if (p.nt == 16) {
+      if constexpr (!TA)
+        return launch_dma<ROLE, TA, 128, 16, 3, 4, 2, 1>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
+    }
     if (p.mt == 128 && p.nt == 128) {
       if (TA)
         return launch_dma<ROLE, TA, 128, 128, 2, 2, 4, 2>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
@@ -544,13 +605,15 @@ hipError_t gemm_tn(Role role, int64_t M, int64_t N, int64_t K, double alpha, con
   hipError_t e;
   if (role == ROLE_GRAM)
     e = launch<ROLE_GRAM, true>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, pp, gate, s);
+  else if (role == ROLE_CHOL)
+    e = launch<ROLE_CHOL, true>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, pp, gate, s);
   else
     e = launch<ROLE_PROJ, true>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, pp, gate, s);
   prof_end(slot, role, s, flops, bytes);
   if (e != hipSuccess || p.nsplit == 1) return e;
   const int64_t total = M * N;
-  int64_t blocks = (total + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
+  int64_t blocks = (total + 63) / 64;
+  if (blocks > 8192) blocks = 8192;
   const int slot2 = prof_begin(s);
   hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, M, N, p.nsplit, part, alpha,
                      beta, C, ldc, gate);
@@ -574,6 +637,9 @@ hipError_t gemm_nn(Role role, int64_t M, int64_t N, int64_t K, double alpha, con
       break;
     case ROLE_TRSM:
       e = launch<ROLE_TRSM, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, gate, s);
+      break;
+    case ROLE_CHOL:
+      e = launch<ROLE_CHOL, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, gate, s);
       break;
     default:
       e = launch<ROLE_SMALL, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, gate, s);
