@@ -76,7 +76,6 @@ __device__ __forceinline__ T wave_sum(T x) {
 // (ld a multiple of 16).
 __device__ __forceinline__ int sw(int row, int col, int ld) { return row * ld + (col ^ (row & 15)); }
 
-constexpr int kKC = 64;           // finished columns per projection/update chunk
 constexpr int kMaxBuckets = 8;
 constexpr int kBatchNMax = 512;
 
@@ -146,16 +145,20 @@ __global__ __launch_bounds__(NW * 64) void batch_kernel(BatchArgs ar) {
   constexpr int LDW = BW + 1;
   constexpr int MAXRT = (NMAX / 16 + NW - 1) / NW;  // update row tiles per wave
   constexpr int MAXCT = BW / 16;
-  constexpr int HSZ = (kKC * BW > NW * 256 ? kKC * BW : NW * 256);
-  static_assert(HSZ >= NMAX, "fallback vector storage");
+  constexpr int RSZ = (NW * 256 > NMAX ? NW * 256 : NMAX);
+  // Two chunk buffers when they fit beside the block, else one.
+  constexpr int PB = ((2 * NMAX * 16 + NMAX * BW) * (int)sizeof(T) <= 100 * 1024) ? 2 : 1;
+  constexpr int TPC = NT / 16;                   // loader threads per chunk column
+  constexpr int PRE = (NMAX + TPC - 1) / TPC;    // chunk elements per loader thread
   using V = typename Mf<T>::V;
 
   __shared__ T sQ[NMAX * BW];
-  __shared__ T sH[HSZ];  // projection chunk; Gram partials; fallback projections
+  __shared__ T sP[PB][NMAX * 16];  // 16 finished columns of P (swizzled, ld 16)
+  __shared__ T sH[16 * BW];        // projection of one chunk
+  __shared__ T sR2[RSZ];           // projection / Gram partial tiles; fallback projections
   __shared__ T sW[BW * LDW];
   __shared__ T sL[2][BW * LDW];
   __shared__ T sDinv[2][BW];
-  __shared__ T sRhs[NMAX];
   __shared__ T sY[NMAX];
   __shared__ T sRed[NW];
   __shared__ int sInt[2];
@@ -182,7 +185,6 @@ __global__ __launch_bounds__(NW * 64) void batch_kernel(BatchArgs ar) {
     int info = 0, flags = 0;
 
     for (int r = tid; r < np; r += NT) {
-      sRhs[r] = (Bv && r < n) ? Bv[r] : T(0);
       sY[r] = T(0);
     }
 
@@ -206,65 +208,100 @@ __global__ __launch_bounds__(NW * 64) void batch_kernel(BatchArgs ar) {
           for (int t = 0; t < MAXRT; ++t)
 #pragma unroll
             for (int c = 0; c < MAXCT; ++c) acc[t][c] = V{};
-          for (int c0 = 0; c0 < s; c0 += kKC) {
-            const int kc = min(kKC, s - c0);
-            // Projection of this chunk: tiles (hc, ct), full reduction over rows.
-            const int units = (kc >> 4) * nct;
-            for (int u = wave; u < units; u += NW) {
-              const int hc = u / nct, ct = u - hc * nct;
-              const T* pcol = A + (size_t)(c0 + 16 * hc + li) * lda;
+          // Chunks of 16 finished columns: staged in LDS (loads of chunk ch+1 in
+          // flight in registers while chunk ch is used), projection split
+          // over rows across waves with partial tiles summed in a fixed order,
+          // update accumulated in registers.
+          const int nch = s >> 4;
+          const int lc = tid / TPC, lr = tid - lc * TPC;
+          const int ks = NW / nct;  // waves per projection tile
+          // Two chunks of loads in flight: ring slot q holds chunk ch (q = ch % 2)
+          // and is refilled with chunk ch + 2 once stored to LDS.
+          T ring0[PRE], ring1[PRE];
+          auto gload = [&](int ch, T (&pre)[PRE]) {
+            const T* pc = A + (size_t)(16 * ch + lc) * lda;
+#pragma unroll
+            for (int u = 0; u < PRE; ++u) {
+              const int r = lr + TPC * u;
+              pre[u] = (r < n) ? pc[r] : T(0);
+            }
+          };
+          auto body = [&](int ch, T (&pre)[PRE]) {
+            T* buf = sP[(PB == 2) ? (ch & 1) : 0];
+#pragma unroll
+            for (int u = 0; u < PRE; ++u) {
+              const int r = lr + TPC * u;
+              if (r < np) buf[sw(r, lc, 16)] = pre[u];
+            }
+            // The second pass adds to the R entries the first pass wrote: fetch
+            // this thread's ones now (16 w <= 16 BW entries per chunk).
+            T rprev[(16 * BW + NT - 1) / NT];
+            if (pass == 1) {
+#pragma unroll
+              for (int u = 0; u < (16 * BW + NT - 1) / NT; ++u) {
+                const int e = tid + u * NT;
+                rprev[u] = (e < 16 * w) ? R[(size_t)(16 * ch + (e & 15)) + (size_t)(s + (e >> 4)) * ldr] : T(0);
+              }
+            }
+            __syncthreads();
+            if (ch + 2 < nch) gload(ch + 2, pre);
+            {
+              const int ct = wave / ks, kp = wave - ct * ks;
               V h = V{};
-              T av[4];
-#pragma unroll
-              for (int t = 0; t < 4; ++t) av[t] = (4 * lg + t < n) ? pcol[4 * lg + t] : T(0);
-              for (int m16 = 0; m16 < np; m16 += 16) {
+              for (int m16 = 16 * kp; m16 < np; m16 += 16 * ks) {
                 const int rb = m16 + 4 * lg;
-                // Loads of the next 16 rows go out before this step's MFMAs.
-                T an[4];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) an[t] = (rb + 16 + t < n) ? pcol[rb + 16 + t] : T(0);
-#pragma unroll
-                for (int t = 0; t < 4; ++t) h = Mf<T>::mma(av[t], sQ[sw(rb + t, 16 * ct + li, BW)], h);
-#pragma unroll
-                for (int t = 0; t < 4; ++t) av[t] = an[t];
+                for (int t = 0; t < 4; ++t)
+                  h = Mf<T>::mma(buf[sw(rb + t, li, 16)], sQ[sw(rb + t, 16 * ct + li, BW)], h);
               }
 #pragma unroll
-              for (int v = 0; v < 4; ++v) {
-                const int hr = 16 * hc + Mf<T>::crow(lg, v);
-                sH[sw(hr, 16 * ct + li, BW)] = h[v];
-                if (pass == 0 && 16 * ct + li < w) R[(size_t)(c0 + hr) + (size_t)(s + 16 * ct + li) * ldr] = h[v];
-              }
+              for (int v = 0; v < 4; ++v) sR2[wave * 256 + Mf<T>::crow(lg, v) * 16 + li] = h[v];
+            }
+            __syncthreads();
+            for (int e = tid; e < 16 * wp; e += NT) {
+              const int k = e & 15, c = e >> 4, ct = c >> 4;
+              T v = T(0);
+              for (int q = 0; q < ks; ++q) v += sR2[(ct * ks + q) * 256 + k * 16 + (c & 15)];
+              sH[sw(k, c, BW)] = v;
+              if (pass == 0 && c < w) R[(size_t)(16 * ch + k) + (size_t)(s + c) * ldr] = v;
             }
             __syncthreads();
             if (pass == 1) {
               // H := H + Hbar L^T for this chunk's rows (L of the first pass).
-              for (int e = tid; e < kc * w; e += NT) {
-                const int k = e % kc, c = e / kc;
-                T add = T(0);
-                for (int p = 0; p <= c; ++p) add += sH[sw(k, p, BW)] * sL[0][c * LDW + p];
-                R[(size_t)(c0 + k) + (size_t)(s + c) * ldr] += add;
+#pragma unroll
+              for (int u = 0; u < (16 * BW + NT - 1) / NT; ++u) {
+                const int e = tid + u * NT;
+                if (e < 16 * w) {
+                  const int k = e & 15, c = e >> 4;
+                  T add = T(0);
+                  for (int p = 0; p <= c; ++p) add += sH[sw(k, p, BW)] * sL[0][c * LDW + p];
+                  R[(size_t)(16 * ch + k) + (size_t)(s + c) * ldr] = rprev[u] + add;
+                }
               }
             }
-            // Update accumulation: acc(rt, ct) += P[rt rows, chunk] Hchunk[:, ct].
-            for (int kk = 0; kk < kc; kk += 4) {
-              const int kcol = c0 + kk + lg;
+#pragma unroll
+            for (int kk = 0; kk < 16; kk += 4) {
               T bv[MAXCT];
 #pragma unroll
               for (int c = 0; c < MAXCT; ++c) bv[c] = (c < nct) ? sH[sw(kk + lg, 16 * c + li, BW)] : T(0);
-              const T* pc = A + (size_t)kcol * lda;
 #pragma unroll
               for (int t = 0; t < MAXRT; ++t) {
                 const int rt = wave + t * NW;
                 if (16 * rt < np) {
-                  const int r = 16 * rt + li;
-                  const T av = (r < n) ? pc[r] : T(0);
+                  const T av = buf[sw(16 * rt + li, kk + lg, 16)];
 #pragma unroll
                   for (int c = 0; c < MAXCT; ++c)
                     if (c < nct) acc[t][c] = Mf<T>::mma(av, bv[c], acc[t][c]);
                 }
               }
             }
-            __syncthreads();
+            if (PB == 1) __syncthreads();  // the single buffer is refilled next
+          };
+          gload(0, ring0);
+          if (nch > 1) gload(1, ring1);
+          for (int ch = 0; ch < nch; ch += 2) {
+            body(ch, ring0);
+            if (ch + 1 < nch) body(ch + 1, ring1);
           }
           // Apply the update (each wave owns its row tiles).
 #pragma unroll
@@ -298,13 +335,13 @@ __global__ __launch_bounds__(NW * 64) void batch_kernel(BatchArgs ar) {
               g = Mf<T>::mma(sQ[sw(rb + t, 16 * ta + li, BW)], sQ[sw(rb + t, 16 * tb + li, BW)], g);
           }
 #pragma unroll
-          for (int v = 0; v < 4; ++v) sH[wave * 256 + Mf<T>::crow(lg, v) * 16 + li] = g[v];
+          for (int v = 0; v < 4; ++v) sR2[wave * 256 + Mf<T>::crow(lg, v) * 16 + li] = g[v];
           __syncthreads();
           for (int e = tid; e < wp * wp; e += NT) {
             const int i = e / wp, jj = e - i * wp;
             const int t = (i >> 4) * nct + (jj >> 4);
             T val = T(0);
-            for (int q = 0; q < ks; ++q) val += sH[(t * ks + q) * 256 + (i & 15) * 16 + (jj & 15)];
+            for (int q = 0; q < ks; ++q) val += sR2[(t * ks + q) * 256 + (i & 15) * 16 + (jj & 15)];
             if (i == jj && i >= w) val = T(1);
             sW[i * LDW + jj] = val;
           }
@@ -339,7 +376,8 @@ __global__ __launch_bounds__(NW * 64) void batch_kernel(BatchArgs ar) {
         }
         for (int c = wave; c < w; c += NW) {
           T d = T(0);
-          for (int r = lane; r < n; r += 64) d += sQ[sw(r, c, BW)] * sRhs[r];
+          if (Bv)
+            for (int r = lane; r < n; r += 64) d += sQ[sw(r, c, BW)] * Bv[r];
           d = wave_sum(d);
           if (lane == 0) sY[s + c] = d;
         }
@@ -353,7 +391,7 @@ __global__ __launch_bounds__(NW * 64) void batch_kernel(BatchArgs ar) {
         flags |= CQR_FLAG_FALLBACK;
         if (info == 0) info = j + 1;
         T* sV = sQ;
-        T* sHv = sH;
+        T* sHv = sR2;
         for (int c = 0; c < w; ++c) {
           const int col = s + c;
           for (int r = tid; r < n; r += NT) sV[r] = A[(size_t)r + (size_t)col * lda];
@@ -407,7 +445,7 @@ __global__ __launch_bounds__(NW * 64) void batch_kernel(BatchArgs ar) {
           if (wave == 0) {
             T d = T(0);
             if (!fail)
-              for (int r = lane; r < n; r += 64) d += sV[r] * sRhs[r];
+              for (int r = lane; r < n; r += 64) d += sV[r] * (Bv ? Bv[r] : T(0));
             d = wave_sum(d);
             if (lane == 0) sY[col] = d;
           }
