@@ -76,7 +76,7 @@ def cpu_baseline(n: int, b: int, seed: int, target_s: float) -> dict:
                       "%.3e flops (Table 1) in %.2f s" % (r0, n, n, b, fl, dt)}
 
 
-def bench_mixed(cqr, torch, n: int, b: int, K: int, W: int, seed: int, fp64_ms: float) -> dict:
+def bench_mixed(cqr, torch, n: int, b: int, K: int, W: int, seed: int, fp64_ms: float, prec: int = 1) -> dict:
     """BF16-MFMA CGS-QR + FP64 iterative refinement on the diagonally dominant
     workload (off-diagonal U[-0.5, 0.5], diagonal = row sum of |.| + 1).
     Value = the same nominal flop count as the FP64 form / (factor + refine)."""
@@ -92,11 +92,11 @@ def bench_mixed(cqr, torch, n: int, b: int, K: int, W: int, seed: int, fp64_ms: 
     R = cqr.colmajor(n, n, device=dev, dtype=torch.float32)
     import ctypes
     nb = ctypes.c_size_t(0)
-    cqr._native.lib().cqr_workspace_size_mixed(n, n, b, cqr.PREC_BF16, ctypes.byref(nb))
+    cqr._native.lib().cqr_workspace_size_mixed(n, n, b, prec, ctypes.byref(nb))
     work = torch.empty(int(nb.value), dtype=torch.uint8, device=dev)
 
     def step():
-        _, _, info = cqr.qr_mixed(Y, b, Q=Q, R=R, work=work)
+        _, _, info = cqr.qr_mixed(Y, b, prec=prec, Q=Q, R=R, work=work)
         x, iters, res = cqr.solve_ir(Y, Q, R, rhs, maxiter=50, tol=16.0)
         return info, iters, res
 
@@ -108,13 +108,13 @@ def bench_mixed(cqr, torch, n: int, b: int, K: int, W: int, seed: int, fp64_ms: 
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / K
     t1 = time.perf_counter()
-    cqr.qr_mixed(Y, b, Q=Q, R=R, work=work)
+    cqr.qr_mixed(Y, b, prec=prec, Q=Q, R=R, work=work)
     torch.cuda.synchronize()
     tf = time.perf_counter() - t1
     # Per-role launch times of one more factorisation (library HIP events).
     cqr.prof_reset()
     cqr.prof_enable(True)
-    cqr.qr_mixed(Y, b, Q=Q, R=R, work=work)
+    cqr.qr_mixed(Y, b, prec=prec, Q=Q, R=R, work=work)
     torch.cuda.synchronize()
     cqr.prof_enable(False)
     roles = {}
@@ -127,7 +127,7 @@ def bench_mixed(cqr, torch, n: int, b: int, K: int, W: int, seed: int, fp64_ms: 
     return {"value": round(flops / el / 1e9, 2), "unit": "GFLOP/s", "ms_per_step": round(el * 1e3, 2),
             "factor_ms": round(tf * 1e3, 2), "speedup_vs_fp64": round(fp64_ms / (el * 1e3), 3) if fp64_ms else None,
             "ir_iterations": [o[1] for o in out], "hpl_scaled_residual": [o[2] for o in out],
-            "info": [o[0] for o in out], "dtype": "bf16 mfma (fp32 acc) + f64 panel + f64 refinement",
+            "info": [o[0] for o in out], "dtype": ("bf16" if prec == 1 else "fp8 e4m3 (per-column pow2 scales)") + " mfma (fp32 acc) + f64 panel + f64 refinement",
             "factor_breakdown": roles,
             "workload": "n=%d, b=%d, off-diagonal U[-0.5,0.5], diagonal = row sum + 1, 1 RHS U[-1,1]" % (n, b)}
 
@@ -447,6 +447,8 @@ def main():
     if not args.no_mixed:
         torch.cuda.empty_cache()
         out["mixed"] = bench_mixed(cqr, torch, n, args.mixed_b, K, W, args.seed, ms_step)
+        torch.cuda.empty_cache()
+        out["mixed_fp8"] = bench_mixed(cqr, torch, n, args.mixed_b, K, W, args.seed, ms_step, prec=2)
     if not args.no_batched:
         out["batched"] = bench_batched(torch, K, W, args.seed, not args.no_tune)
     if not args.no_adjoint:

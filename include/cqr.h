@@ -41,6 +41,7 @@ extern "C" {
 
 /* Precision forms of cqr_factor_mixed. */
 #define CQR_PREC_BF16 1 /* projections and updates on BF16 MFMA with FP32 accumulation */
+#define CQR_PREC_FP8 2  /* ... on FP8 (OCP E4M3) MFMA, per-column power-of-two scales, FP32 accumulation */
 
 /* Bits of the per-block flags written by cqr_factor. */
 #define CQR_FLAG_FALLBACK 1 /* the block's Cholesky factorisation broke down; redone by CGS2 */

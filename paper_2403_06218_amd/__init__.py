@@ -21,6 +21,7 @@ from ._native import CqrError
 FLAG_FALLBACK = 1
 FLAG_ZERO_COL = 2
 PREC_BF16 = 1
+PREC_FP8 = 2
 
 __all__ = ["colmajor", "workspace_size", "qr", "orth", "orth_against", "solve", "qr_mixed", "solve_ir",
            "synth_uniform",
@@ -144,8 +145,9 @@ def solve(Q: torch.Tensor, R: torch.Tensor, rhs: torch.Tensor, work: torch.Tenso
 
 def qr_mixed(Y: torch.Tensor, b: int, prec: int = PREC_BF16, Q: torch.Tensor | None = None,
              R: torch.Tensor | None = None, work: torch.Tensor | None = None):
-    """Low-precision CGS-QR of column-major FP64 Y (not modified): BF16 MFMA
-    projections/updates, FP64 panel.  Returns (Q (FP32), R (FP32), info)."""
+    """Low-precision CGS-QR of column-major FP64 Y (not modified): BF16
+    (prec=PREC_BF16) or FP8 E4M3 (prec=PREC_FP8) MFMA projections/updates, FP64
+    panel.  Returns (Q (FP32), R (FP32), info)."""
     q, r = Y.shape
     if Q is None:
         Q = colmajor(q, r, device=Y.device, dtype=torch.float32)

@@ -32,6 +32,7 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void;
+typedef unsigned char fp8_t;  // OCP E4M3 byte
 
 constexpr int kBKT = 64;  // k per stage
 
@@ -202,16 +203,26 @@ gemm_bf16_kernel(int64_t M, int64_t N, int64_t K, float alpha, const __bf16* __r
 // served by L2) into a 2-slot ring.  Each wave's vmcnt then counts only its
 // own operand, so A keeps 5 stages (80 KiB) in flight while B is waited for
 // one stage ahead; the two rings fill the 160 KiB of LDS.
-template <int ROLE, int OUT>
+//
+// E is __bf16 (v_mfma_f32_16x16x32_bf16, 64 k per stage) or fp8 (OCP E4M3
+// bytes, v_mfma_f32_16x16x32_fp8_fp8, 128 k per stage); both give 128 bytes
+// per column per stage, so the LDS layout is the same.  rs / cs (may be
+// NULL) multiply accumulator row m / column n before alpha: the inverse
+// power-of-two scales of the FP8 operands.
+template <typename E, int ROLE, int OUT>
 __global__ void __launch_bounds__(512, 1)
-gemm_bf16_wide_kernel(int64_t M, int64_t N, int64_t K, float alpha, const __bf16* __restrict__ A, int64_t lda,
-                      const __bf16* __restrict__ B, int64_t ldb, float beta, void* C, int64_t ldc, int64_t kchunk,
-                      float* __restrict__ part, const int* __restrict__ gate) {
+gemm_lp_wide_kernel(int64_t M, int64_t N, int64_t K, float alpha, const E* __restrict__ A, int64_t lda,
+                    const E* __restrict__ B, int64_t ldb, float beta, void* C, int64_t ldc, int64_t kchunk,
+                    float* __restrict__ part, const float* __restrict__ rs, const float* __restrict__ cs,
+                    const int* __restrict__ gate) {
   if (gate != nullptr && *gate != 0) return;
+  constexpr bool F8 = sizeof(E) == 1;
+  constexpr int KST = F8 ? 128 : kBKT;  // k per stage
+  constexpr int EPC = F8 ? 16 : 8;      // elements per 16-byte chunk
   constexpr int MT = 128, NT = 256, WM = 2;
   constexpr int WTM = 64, WTN = 64, SM = 4, SN = 4;
   constexpr int SA = 6, SB = 2;
-  constexpr int ASTAGE = MT * kBKT * 2, BSTAGE = NT * kBKT * 2;
+  constexpr int ASTAGE = MT * 128, BSTAGE = NT * 128;
   constexpr int AINS = ASTAGE / 1024 / 4, BINS = BSTAGE / 1024 / 4;  // DMA instructions per loading wave
   __shared__ __attribute__((aligned(16))) char sA0[ASTAGE], sA1[ASTAGE], sA2[ASTAGE], sA3[ASTAGE], sA4[ASTAGE],
       sA5[ASTAGE];
@@ -240,7 +251,7 @@ gemm_bf16_wide_kernel(int64_t M, int64_t N, int64_t K, float alpha, const __bf16
   const int64_t n0 = (int64_t)blockIdx.y * NT;
   const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
   const int64_t kend = (K < kbeg + kchunk) ? K : kbeg + kchunk;
-  const int nst = (kend > kbeg) ? (int)((kend - kbeg) / kBKT) : 0;
+  const int nst = (kend > kbeg) ? (int)((kend - kbeg) / KST) : 0;
 
   // Source offsets of this lane's chunks (clamped past the matrix edge).
   constexpr int INS = AINS > BINS ? AINS : BINS;
@@ -251,20 +262,20 @@ gemm_bf16_wide_kernel(int64_t M, int64_t N, int64_t K, float alpha, const __bf16
     const int x = p / 8, c = (p % 8) ^ ((x >> 1) & 7);
     if (aloader) {
       const int64_t m = (m0 + x < M) ? m0 + x : M - 1;
-      off[t] = 8 * c + m * lda;
+      off[t] = EPC * c + m * lda;
     } else {
       const int64_t n = (n0 + x < N) ? n0 + x : N - 1;
-      off[t] = 8 * c + n * ldb;
+      off[t] = EPC * c + n * ldb;
     }
   }
   auto issueA = [&](int st, auto slot) {
-    const int64_t k0 = kbeg + (int64_t)st * kBKT;
+    const int64_t k0 = kbeg + (int64_t)st * KST;
     char* la = slotA(slot);
 #pragma unroll
     for (int t = 0; t < AINS; ++t) dma16(A + k0 + off[t], la + (lw * AINS + t) * 1024);
   };
   auto issueB = [&](int st, auto slot) {
-    const int64_t k0 = kbeg + (int64_t)st * kBKT;
+    const int64_t k0 = kbeg + (int64_t)st * KST;
     char* lb = slotB(slot);
 #pragma unroll
     for (int t = 0; t < BINS; ++t) dma16(B + k0 + off[t], lb + (lw * BINS + t) * 1024);
@@ -279,19 +290,38 @@ gemm_bf16_wide_kernel(int64_t M, int64_t N, int64_t K, float alpha, const __bf16
   auto compute = [&](auto sa, auto sb) {
     const char* cA = slotA(sa);
     const char* cB = slotB(sb);
+    if constexpr (F8) {
+      // k-step h covers bytes 32 h .. 32 h + 31 of each column; lane group lg
+      // supplies bytes 32 h + 8 lg .. + 7: half of chunk 2 h + lg / 2.
 #pragma unroll
-    for (int h = 0; h < kBKT / 32; ++h) {
-      const int c = 4 * h + lg;
-      bf16x8 af[SM], bf[SN];
+      for (int h = 0; h < 4; ++h) {
+        const int c = 2 * h + (lg >> 1), sub = 8 * (lg & 1);
+        long af[SM], bf[SN];
 #pragma unroll
-      for (int i = 0; i < SM; ++i) af[i] = *(const bf16x8*)(cA + chunk_off(c, wm * WTM + i * 16 + li));
+        for (int i = 0; i < SM; ++i) af[i] = *(const long*)(cA + chunk_off(c, wm * WTM + i * 16 + li) + sub);
 #pragma unroll
-      for (int j = 0; j < SN; ++j) bf[j] = *(const bf16x8*)(cB + chunk_off(c, wn * WTN + j * 16 + li));
+        for (int j = 0; j < SN; ++j) bf[j] = *(const long*)(cB + chunk_off(c, wn * WTN + j * 16 + li) + sub);
 #pragma unroll
-      for (int i = 0; i < SM; ++i)
+        for (int i = 0; i < SM; ++i)
 #pragma unroll
-        for (int j = 0; j < SN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < SN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(af[i], bf[j], acc[i][j], 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int h = 0; h < kBKT / 32; ++h) {
+        const int c = 4 * h + lg;
+        bf16x8 af[SM], bf[SN];
+#pragma unroll
+        for (int i = 0; i < SM; ++i) af[i] = *(const bf16x8*)(cA + chunk_off(c, wm * WTM + i * 16 + li));
+#pragma unroll
+        for (int j = 0; j < SN; ++j) bf[j] = *(const bf16x8*)(cB + chunk_off(c, wn * WTN + j * 16 + li));
+#pragma unroll
+        for (int i = 0; i < SM; ++i)
+#pragma unroll
+          for (int j = 0; j < SN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+      }
     }
   };
 
@@ -350,11 +380,12 @@ gemm_bf16_wide_kernel(int64_t M, int64_t N, int64_t K, float alpha, const __bf16
       const int64_t n = n0 + wn * WTN + j * 16 + li;
       const int64_t mb = m0 + wm * WTM + i * 16 + 4 * lg;
       if (n >= N) continue;
+      const float csn = cs ? cs[n] : 1.f;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t m = mb + v;
         if (m >= M) continue;
-        const float val = acc[i][j][v];
+        const float val = acc[i][j][v] * (rs ? rs[m] : 1.f) * csn;
         if constexpr (OUT == 0) {
           part[zoff + m + n * M] = val;
         } else if constexpr (OUT == 1) {
@@ -410,8 +441,8 @@ hipError_t launch_bf16_tile(int64_t M, int64_t N, int64_t K, float alpha, const 
                             float* part, const int* gate, hipStream_t s) {
   if (M > 64 && N > 128) {
     const dim3 grid((unsigned)((M + 127) / 128), (unsigned)((N + 255) / 256), (unsigned)nsplit);
-    hipLaunchKernelGGL((gemm_bf16_wide_kernel<ROLE, OUT>), grid, dim3(512), 0, s, M, N, K, alpha, A, lda, B, ldb,
-                       beta, C, ldc, kchunk, part, gate);
+    hipLaunchKernelGGL((gemm_lp_wide_kernel<__bf16, ROLE, OUT>), grid, dim3(512), 0, s, M, N, K, alpha, A, lda, B,
+                       ldb, beta, C, ldc, kchunk, part, (const float*)nullptr, (const float*)nullptr, gate);
     return hipGetLastError();
   }
   if (M > 64 && N > 64)
@@ -499,6 +530,78 @@ hipError_t gemm_bf16_tn(Role role, int64_t M, int64_t N, int64_t K, float alpha,
   else
     hipLaunchKernelGGL(splitk_reduce_f32_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s, M, N, nsplit, part,
                        alpha, beta, (float*)C, ldc, gate);
+  e = hipGetLastError();
+  prof_end(slot2, ROLE_REDUCE, s, 0.0, 4.0 * (double)total * (nsplit + (beta != 0.f ? 2 : 1)));
+  return e;
+}
+
+bool gemm_fp8_supported(const void* A, int64_t lda, const void* B, int64_t ldb, int64_t K) {
+  return !(reinterpret_cast<uintptr_t>(A) & 15) && !(reinterpret_cast<uintptr_t>(B) & 15) && lda % 16 == 0 &&
+         ldb % 16 == 0 && K % 128 == 0;
+}
+
+hipError_t gemm_fp8_tn(Role role, int64_t M, int64_t N, int64_t K, float alpha, const uint8_t* A, int64_t lda,
+                       const uint8_t* B, int64_t ldb, float beta, void* C, int64_t ldc, bool c_is_f64, const float* rs,
+                       const float* cs, float* part, size_t part_cap, const int* gate, hipStream_t s, double flops) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  if (!gemm_fp8_supported(A, lda, B, ldb, K)) return hipErrorInvalidValue;
+  // Always the 128 x 256 tile (columns past N are clamped and not stored).
+  int nsplit = 1;
+  if (part != nullptr) {
+    const int64_t tiles = ((M + 127) / 128) * ((N + 255) / 256);
+    int64_t max_split = K / (4 * 128);
+    const int64_t by_cap = (int64_t)(part_cap / (size_t)(M * N));
+    if (max_split > by_cap) max_split = by_cap;
+    if (max_split > 256) max_split = 256;
+    double best = 0.0;
+    for (int64_t sp = 1; sp <= (max_split < 1 ? 1 : max_split); ++sp) {
+      const int64_t wgs = tiles * sp;
+      const int64_t rounds = (wgs + 255) / 256;
+      const double eff = (double)wgs / (double)(rounds * 256);
+      if (eff > best + 0.02) {
+        best = eff;
+        nsplit = (int)sp;
+      }
+    }
+  }
+  int64_t kchunk = K > 0 ? K : 128;
+  if (nsplit > 1) {
+    kchunk = (K + nsplit - 1) / nsplit;
+    kchunk = (kchunk + 127) / 128 * 128;
+    nsplit = (int)((K + kchunk - 1) / kchunk);
+  }
+  const double bytes = ((double)K * M + (double)K * N) + (c_is_f64 ? 8.0 : 4.0) * (double)M * N *
+                                                          (beta != 0.f ? 2.0 : 1.0);
+  const dim3 grid((unsigned)((M + 127) / 128), (unsigned)((N + 255) / 256), (unsigned)nsplit);
+  const fp8_t* a8 = (const fp8_t*)A;
+  const fp8_t* b8 = (const fp8_t*)B;
+  const int slot = prof_begin(s);
+  if (nsplit > 1) {
+    if (role == ROLE_UPDATE)
+      hipLaunchKernelGGL((gemm_lp_wide_kernel<fp8_t, ROLE_UPDATE, 0>), grid, dim3(512), 0, s, M, N, K, alpha, a8, lda,
+                         b8, ldb, beta, C, ldc, kchunk, part, rs, cs, gate);
+    else
+      hipLaunchKernelGGL((gemm_lp_wide_kernel<fp8_t, ROLE_PROJ, 0>), grid, dim3(512), 0, s, M, N, K, alpha, a8, lda,
+                         b8, ldb, beta, C, ldc, kchunk, part, rs, cs, gate);
+  } else if (c_is_f64) {
+    if (role == ROLE_UPDATE)
+      hipLaunchKernelGGL((gemm_lp_wide_kernel<fp8_t, ROLE_UPDATE, 2>), grid, dim3(512), 0, s, M, N, K, alpha, a8, lda,
+                         b8, ldb, beta, C, ldc, kchunk, part, rs, cs, gate);
+    else
+      hipLaunchKernelGGL((gemm_lp_wide_kernel<fp8_t, ROLE_PROJ, 2>), grid, dim3(512), 0, s, M, N, K, alpha, a8, lda,
+                         b8, ldb, beta, C, ldc, kchunk, part, rs, cs, gate);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  prof_end(slot, role, s, flops, bytes);
+  if (e != hipSuccess || nsplit == 1) return e;
+  const int64_t total = M * N;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  const int slot2 = prof_begin(s);
+  hipLaunchKernelGGL(splitk_reduce_f32_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, M, N, nsplit, part,
+                     alpha, beta, (double*)C, ldc, gate);
   e = hipGetLastError();
   prof_end(slot2, ROLE_REDUCE, s, 0.0, 4.0 * (double)total * (nsplit + (beta != 0.f ? 2 : 1)));
   return e;

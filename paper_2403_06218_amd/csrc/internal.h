@@ -55,6 +55,16 @@ hipError_t gemm_bf16_tn(Role role, int64_t M, int64_t N, int64_t K, float alpha,
                         const __bf16* B, int64_t ldb, float beta, void* C, int64_t ldc, bool c_is_f64, float* part,
                         size_t part_cap, const int* gate, hipStream_t s, double flops);
 
+// FP8 (OCP E4M3 bytes) GEMM with FP32 accumulation, same contract as
+// gemm_bf16_tn (C FP64 only, or FP32 split-K partials reduced into FP64 C),
+// with optional per-row rs[m] and per-column cs[n] multipliers of A^T B (the
+// inverse power-of-two scales of the operands).  Requires 16-byte aligned A
+// and B, lda and ldb multiples of 16, K a multiple of 128.
+bool gemm_fp8_supported(const void* A, int64_t lda, const void* B, int64_t ldb, int64_t K);
+hipError_t gemm_fp8_tn(Role role, int64_t M, int64_t N, int64_t K, float alpha, const uint8_t* A, int64_t lda,
+                       const uint8_t* B, int64_t ldb, float beta, void* C, int64_t ldc, bool c_is_f64, const float* rs,
+                       const float* cs, float* part, size_t part_cap, const int* gate, hipStream_t s, double flops);
+
 // Lower Cholesky W = L L^T of a b x b SPD matrix (b <= 128) and the inverse of
 // L, in one workgroup.  Writes LT = L^T and XT = (L^{-1})^T (both b x b,
 // leading dimension b, upper triangular with zero strictly-lower part).  On a

@@ -1,11 +1,12 @@
 // Low-precision form of the factorisation and the FP64 iterative refinement.
 //
 // cqr_factor_mixed runs CGS-QR (Algorithms 3-5) with the projections
-// (Alg. 5 S1/S6) and updates (S2/S7) on BF16 MFMA with FP32 accumulation,
-// while the working block, its Gram matrices, Cholesky factors and TRSMs stay
-// in FP64.  Finished columns are kept in BF16 twice (column-major for the
-// projections' A^T, transposed for the updates' A) and returned as FP32 Q; R
-// is returned in FP32.  Y itself is read, never written, so that the
+// (Alg. 5 S1/S6) and updates (S2/S7) on BF16 or FP8 (OCP E4M3) MFMA with FP32
+// accumulation, while the working block, its Gram matrices, Cholesky factors
+// and TRSMs stay in FP64.  Finished columns are kept in the low precision
+// twice (column-major for the projections' A^T, transposed for the updates'
+// A) and returned as FP32 Q; R is returned in FP32.  FP8 operands carry one
+// power-of-two scale per column, undone exactly in the GEMM epilogue.  Y itself is read, never written, so that the
 // refinement can compute residuals against it.
 //
 // cqr_solve_ir: x_0 = 0, then repeatedly d = R^{-1} Q^T r (FP32 factors, FP64
@@ -35,16 +36,26 @@ struct MixedWork {
   double* T;        // q x b after the first pass
   double* H;        // r x b projections, first pass (FP64)
   double* Hb;       // r x b projections, second pass
+  // BF16 form
   __bf16* P16;      // qp x rp: finished columns, column-major (ld qp)
   __bf16* P16T;     // rp x qp: finished columns transposed (ld rp)
   __bf16* B16;      // qp x b: BF16 copy of the block being projected (ld qp)
   __bf16* H16;      // rp x b: BF16 copy of a projection (ld rp)
+  // FP8 form (OCP E4M3 bytes, each column with a power-of-two scale)
+  uint8_t* P8;      // qp x rp
+  uint8_t* P8T;     // rp x qp
+  uint8_t* B8;      // qp x b
+  uint8_t* H8;      // rp x b
+  float* pinv;      // rp: inverse scale of each finished column
+  float* binv;      // b: inverse scales of the block's columns
+  float* hinv;      // b: inverse scales of a projection's columns
+  double* cmax;     // b: column maxima
   float* part;      // split-K partial sums
   size_t part_cap;
   int64_t qp, rp;
 };
 
-size_t mixed_layout(int64_t q, int64_t r, int64_t b, char* base, MixedWork* w) {
+size_t mixed_layout(int64_t q, int64_t r, int64_t b, int prec, char* base, MixedWork* w) {
   size_t off = 0;
   auto take = [&](size_t bytes) {
     char* p = base ? base + off : nullptr;
@@ -53,8 +64,10 @@ size_t mixed_layout(int64_t q, int64_t r, int64_t b, char* base, MixedWork* w) {
   };
   MixedWork tmp;
   MixedWork* o = w ? w : &tmp;
-  o->qp = up(q > 0 ? q : 1, 64);
-  o->rp = up(r > 0 ? r : 1, 64);
+  memset(o, 0, sizeof(*o));
+  const int64_t pad = (prec == CQR_PREC_FP8) ? 128 : 64;
+  o->qp = up(q > 0 ? q : 1, pad);
+  o->rp = up(r > 0 ? r : 1, pad);
   const size_t bb = (size_t)b * b * 8, qb = (size_t)q * b * 8;
   o->status = (int*)take(64);
   o->W = (double*)take(bb);
@@ -67,10 +80,21 @@ size_t mixed_layout(int64_t q, int64_t r, int64_t b, char* base, MixedWork* w) {
   o->T = (double*)take(qb);
   o->H = (double*)take((size_t)o->rp * b * 8);
   o->Hb = (double*)take((size_t)o->rp * b * 8);
-  o->P16 = (__bf16*)take((size_t)o->qp * o->rp * 2);
-  o->P16T = (__bf16*)take((size_t)o->rp * o->qp * 2);
-  o->B16 = (__bf16*)take((size_t)o->qp * b * 2);
-  o->H16 = (__bf16*)take((size_t)o->rp * b * 2);
+  if (prec == CQR_PREC_FP8) {
+    o->P8 = (uint8_t*)take((size_t)o->qp * o->rp);
+    o->P8T = (uint8_t*)take((size_t)o->rp * o->qp);
+    o->B8 = (uint8_t*)take((size_t)o->qp * b);
+    o->H8 = (uint8_t*)take((size_t)o->rp * b);
+    o->pinv = (float*)take((size_t)o->rp * 4);
+    o->binv = (float*)take((size_t)b * 4);
+    o->hinv = (float*)take((size_t)b * 4);
+    o->cmax = (double*)take((size_t)b * 8);
+  } else {
+    o->P16 = (__bf16*)take((size_t)o->qp * o->rp * 2);
+    o->P16T = (__bf16*)take((size_t)o->rp * o->qp * 2);
+    o->B16 = (__bf16*)take((size_t)o->qp * b * 2);
+    o->H16 = (__bf16*)take((size_t)o->rp * b * 2);
+  }
   o->part_cap = (size_t)16 << 20;
   o->part = (float*)take(o->part_cap * 4);
   return off;
@@ -87,6 +111,102 @@ to_bf16_kernel(int64_t rows, int64_t rows_pad, int64_t cols, const double* __res
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = idx % rows_pad, j = idx / rows_pad;
     dst[i + j * ldd] = (i < rows) ? (__bf16)src[i + j * lds] : (__bf16)0.0f;
+  }
+}
+
+// ---------------------------------------------------------------- FP8 operands
+// OCP E4M3 (the gfx950 FP8 format: largest finite 448, no saturation in the
+// conversion instruction, so values are clamped first).  Every operand column
+// is scaled by a power of two s = 2^(8 - e), with max |column| = f 2^e,
+// f in [0.5, 1), which maps the column maximum into [128, 256); the GEMM
+// epilogue multiplies by 1/s exactly.
+
+__device__ __forceinline__ uint8_t to_e4m3(float v) {
+  v = fminf(fmaxf(v, -448.f), 448.f);
+  return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.f, 0, false) & 0xff);
+}
+
+__device__ __forceinline__ float pow2_scale(double m) {
+  if (!(m > 0.0) || !(m < 1e300)) return 1.f;
+  int e;
+  frexp(m, &e);
+  e = e < -110 ? -110 : (e > 120 ? 120 : e);  // keeps s and 1/s normal floats
+  return ldexpf(1.f, 8 - e);
+}
+
+// cmax[j] = max_i |src(i, j) * rowscale[i]| (rowscale may be NULL); one
+// workgroup per column.
+__global__ void __launch_bounds__(256)
+colmax_kernel(int64_t rows, const double* __restrict__ src, int64_t lds, const float* __restrict__ rowscale,
+              double* __restrict__ cmax, const int* __restrict__ gate) {
+  if (gate != nullptr && *gate != 0) return;
+  __shared__ double red[256];
+  const int j = blockIdx.x, t = threadIdx.x;
+  const double* col = src + (int64_t)j * lds;
+  double m = 0.0;
+  for (int64_t i = t; i < rows; i += 256) {
+    const double v = fabs(col[i] * (rowscale ? (double)rowscale[i] : 1.0));
+    m = v > m ? v : m;
+  }
+  red[t] = m;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) red[t] = red[t + h] > red[t] ? red[t + h] : red[t];
+    __syncthreads();
+  }
+  if (t == 0) cmax[j] = red[0];
+}
+
+// dst (FP8, rows_pad x cols, ld ldd) = e4m3(src(i, j) * rowscale[i] * s_j)
+// with s_j from cmax[j]; colinv[j] = 1 / s_j; rows >= rows are zero.
+__global__ void __launch_bounds__(256)
+to_fp8_kernel(int64_t rows, int64_t rows_pad, int64_t cols, const double* __restrict__ src, int64_t lds,
+              const float* __restrict__ rowscale, const double* __restrict__ cmax, uint8_t* __restrict__ dst,
+              int64_t ldd, float* __restrict__ colinv, const int* __restrict__ gate) {
+  if (gate != nullptr && *gate != 0) return;
+  const int64_t total = rows_pad * cols;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx % rows_pad, j = idx / rows_pad;
+    const float sc = pow2_scale(cmax[j]);
+    uint8_t v = 0;
+    if (i < rows) v = to_e4m3((float)(src[i + j * lds] * (rowscale ? (double)rowscale[i] : 1.0) * (double)sc));
+    dst[i + j * ldd] = v;
+    if (i == 0) colinv[j] = 1.f / sc;
+  }
+}
+
+// A finished block Qj (q x w, FP64): Q32[:, c0:c0+w] = float(Qj),
+// P8[:, c0 + j] = e4m3(Qj[:, j] s_j) and P8T[c0 + j, :] its transpose, with
+// s_j from cmax[j]; pinv[c0 + j] = 1 / s_j.
+__global__ void __launch_bounds__(256)
+finish_block_fp8_kernel(int64_t q, int w, const double* __restrict__ Qj, int64_t ldj, float* __restrict__ Q32,
+                        int64_t ldq, uint8_t* __restrict__ P8, int64_t ldp, uint8_t* __restrict__ P8T, int64_t ldpt,
+                        const double* __restrict__ cmax, float* __restrict__ pinv, int64_t c0,
+                        const int* __restrict__ gate) {
+  if (gate != nullptr && *gate != 0) return;
+  __shared__ uint8_t tile[64][65];
+  const int64_t i0 = (int64_t)blockIdx.x * 64;
+  const int j0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+  for (int jj = ty; jj < 64; jj += 4) {
+    const int64_t i = i0 + tx;
+    const int j = j0 + jj;
+    if (i < q && j < w) {
+      const double v = Qj[i + (int64_t)j * ldj];
+      const float sc = pow2_scale(cmax[j]);
+      Q32[i + (c0 + j) * ldq] = (float)v;
+      const uint8_t h = to_e4m3((float)(v * (double)sc));
+      P8[i + (c0 + j) * ldp] = h;
+      tile[jj][tx] = h;
+      if (i == 0) pinv[c0 + j] = 1.f / sc;
+    }
+  }
+  __syncthreads();
+  for (int ii = ty; ii < 64; ii += 4) {
+    const int64_t i = i0 + ii;
+    const int j = j0 + tx;
+    if (i < q && j < w) P8T[(c0 + j) + i * ldpt] = tile[tx][ii];
   }
 }
 
@@ -293,7 +413,7 @@ __global__ void __launch_bounds__(256) axpy_kernel(int64_t n, const double* __re
 
 // ---------------------------------------------------------------- factor
 
-// One column block of the mixed factorisation (see the file comment).
+// One column block of the BF16 form (see the file comment).
 int mixed_block(int64_t q, int64_t w, int64_t s, const double* Yj, int64_t ldy, float* Q32, int64_t ldq, float* R32,
                 int64_t ldr, const MixedWork& ws, int blk, hipStream_t st) {
   const int* gate = ws.status;
@@ -343,6 +463,63 @@ int mixed_block(int64_t q, int64_t w, int64_t s, const double* Yj, int64_t ldy, 
   return CQR_OK;
 }
 
+// One column block of the FP8 form: as mixed_block, with the projections and
+// updates on FP8 operands scaled per column.
+int mixed_block_fp8(int64_t q, int64_t w, int64_t s, const double* Yj, int64_t ldy, float* Q32, int64_t ldq,
+                    float* R32, int64_t ldr, const MixedWork& ws, int blk, hipStream_t st) {
+  const int* gate = ws.status;
+  const double dq = (double)q, dw = (double)w, ds = (double)s;
+  const int64_t sp = up(s, 128);
+  MX_TRY(copy_matrix(q, w, Yj, ldy, ws.Qj, q, gate, st));
+  for (int pass = 0; pass < 2; ++pass) {
+    double* X = pass == 0 ? ws.Qj : ws.T;
+    double* Hx = pass == 0 ? ws.H : ws.Hb;
+    if (s > 0) {
+      hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)w), dim3(256), 0, st, q, X, q, (const float*)nullptr, ws.cmax,
+                         gate);
+      MX_TRY(hipGetLastError());
+      hipLaunchKernelGGL(to_fp8_kernel, dim3(grid_of(ws.qp * w)), dim3(256), 0, st, q, ws.qp, w, X, q,
+                         (const float*)nullptr, ws.cmax, ws.B8, ws.qp, ws.binv, gate);
+      MX_TRY(hipGetLastError());
+      // S1/S6: H = P^T X, undone scales: rows by 1/s_P, columns by 1/s_X.
+      MX_TRY(gemm_fp8_tn(ROLE_PROJ, s, w, ws.qp, 1.0f, ws.P8, ws.qp, ws.B8, ws.qp, 0.0f, Hx, ws.rp, true, ws.pinv,
+                         ws.binv, ws.part, ws.part_cap, gate, st, 2.0 * dw * dq * ds));
+      // H' = diag(1/s_P) H, then per-column scales for its FP8 copy.
+      hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)w), dim3(256), 0, st, s, Hx, ws.rp, ws.pinv, ws.cmax, gate);
+      MX_TRY(hipGetLastError());
+      hipLaunchKernelGGL(to_fp8_kernel, dim3(grid_of(sp * w)), dim3(256), 0, st, s, sp, w, Hx, ws.rp, ws.pinv,
+                         ws.cmax, ws.H8, ws.rp, ws.hinv, gate);
+      MX_TRY(hipGetLastError());
+      // S2/S7: X -= (P diag(s_P)) (diag(1/s_P) H), columns undone by 1/s_H.
+      MX_TRY(gemm_fp8_tn(ROLE_UPDATE, q, w, sp, -1.0f, ws.P8T, ws.rp, ws.H8, ws.rp, 1.0f, X, q, true, nullptr,
+                         ws.hinv, nullptr, 0, gate, st, 2.0 * dw * dq * ds));
+    }
+    MX_TRY(gemm_tn(ROLE_GRAM, w, w, q, 1.0, X, q, X, q, 0.0, ws.W, w, (double*)ws.part, ws.part_cap / 2, gate, st,
+                   (s > 0 ? 2.0 : 1.0) * dw * dw * dq));
+    MX_TRY(chol_inv_wide((int)w, ws.W, w, pass == 0 ? ws.LT1 : ws.LT2, pass == 0 ? ws.XT1 : ws.XT2, ws.Rjj, ws.status,
+                         pass + 1, blk, st));
+    MX_TRY(gemm_nn(ROLE_TRSM, q, w, w, 1.0, X, q, pass == 0 ? ws.XT1 : ws.XT2, w, 0.0, pass == 0 ? ws.T : ws.Qj, q,
+                   gate, st, dw * dw * dq));
+  }
+  MX_TRY(gemm_nn(ROLE_SMALL, w, w, w, 1.0, ws.LT2, w, ws.LT1, w, 0.0, ws.Rjj, w, gate, st, dw * dw * dw));
+  if (s > 0) {
+    MX_TRY(gemm_nn(ROLE_SMALL, s, w, w, 1.0, ws.Hb, ws.rp, ws.LT1, w, 1.0, ws.H, ws.rp, gate, st, dw * ds));
+    hipLaunchKernelGGL(to_f32_kernel, dim3(grid_of(s * w)), dim3(256), 0, st, s, w, ws.H, ws.rp, R32 + s * ldr, ldr,
+                       gate);
+    MX_TRY(hipGetLastError());
+  }
+  hipLaunchKernelGGL(to_f32_kernel, dim3(grid_of(w * w)), dim3(256), 0, st, w, w, ws.Rjj, w, R32 + s + s * ldr, ldr,
+                     gate);
+  MX_TRY(hipGetLastError());
+  hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)w), dim3(256), 0, st, q, ws.Qj, q, (const float*)nullptr, ws.cmax,
+                     gate);
+  MX_TRY(hipGetLastError());
+  hipLaunchKernelGGL(finish_block_fp8_kernel, dim3((unsigned)((q + 63) / 64), (unsigned)((w + 63) / 64)), dim3(256),
+                     0, st, q, (int)w, ws.Qj, q, Q32, ldq, ws.P8, ws.qp, ws.P8T, ws.rp, ws.cmax, ws.pinv, s, gate);
+  MX_TRY(hipGetLastError());
+  return CQR_OK;
+}
+
 }  // namespace
 }  // namespace cqr
 
@@ -355,9 +532,9 @@ int cqr_workspace_size_mixed(int64_t q, int64_t r, int64_t b, int prec, size_t* 
   if (r < 0 || r > q) return -2;
   if (b < 1) return -3;
   if (b > 256 || b % 16 != 0) return CQR_ERR_UNSUPPORTED;
-  if (prec != CQR_PREC_BF16) return CQR_ERR_UNSUPPORTED;
+  if (prec != CQR_PREC_BF16 && prec != CQR_PREC_FP8) return CQR_ERR_UNSUPPORTED;
   if (!bytes) return -5;
-  *bytes = mixed_layout(q, r, b, nullptr, nullptr);
+  *bytes = mixed_layout(q, r, b, prec, nullptr, nullptr);
   return CQR_OK;
 }
 
@@ -367,7 +544,7 @@ int cqr_factor_mixed(int64_t q, int64_t r, int64_t b, int prec, const double* Y,
   if (r < 0 || r > q) return -2;
   if (b < 1) return -3;
   if (b > 256 || b % 16 != 0) return CQR_ERR_UNSUPPORTED;
-  if (prec != CQR_PREC_BF16) return CQR_ERR_UNSUPPORTED;
+  if (prec != CQR_PREC_BF16 && prec != CQR_PREC_FP8) return CQR_ERR_UNSUPPORTED;
   if (!Y && q * r > 0) return -5;
   if (ldy < (q > 1 ? q : 1) || (ldy & 1)) return ldy < q ? -6 : CQR_ERR_UNSUPPORTED;
   if (!Q && q * r > 0) return -7;
@@ -377,10 +554,10 @@ int cqr_factor_mixed(int64_t q, int64_t r, int64_t b, int prec, const double* Y,
   if (reinterpret_cast<uintptr_t>(Y) & 15) return CQR_ERR_UNSUPPORTED;
   if (info) *info = 0;
   if (r == 0) return CQR_OK;
-  const size_t need = mixed_layout(q, r, b, nullptr, nullptr);
+  const size_t need = mixed_layout(q, r, b, prec, nullptr, nullptr);
   if (!work || work_bytes < need) return CQR_ERR_WORKSPACE;
   MixedWork ws;
-  mixed_layout(q, r, b, (char*)work, &ws);
+  mixed_layout(q, r, b, prec, (char*)work, &ws);
   hipStream_t st = (hipStream_t)stream;
   // Zero the whole workspace: the BF16 buffers rely on zero padding and on
   // not-yet-finished columns reading as zero.
@@ -392,7 +569,8 @@ int cqr_factor_mixed(int64_t q, int64_t r, int64_t b, int prec, const double* Y,
   for (int64_t blk = 0; blk < k; ++blk) {
     const int64_t s = blk * b;
     const int64_t w = (r - s < b) ? r - s : b;
-    const int rc = mixed_block(q, w, s, Y + s * ldy, ldy, Q, ldq, R, ldr, ws, (int)blk, st);
+    const int rc = (prec == CQR_PREC_FP8) ? mixed_block_fp8(q, w, s, Y + s * ldy, ldy, Q, ldq, R, ldr, ws, (int)blk, st)
+                                          : mixed_block(q, w, s, Y + s * ldy, ldy, Q, ldq, R, ldr, ws, (int)blk, st);
     if (rc) return rc;
   }
   int stv[2] = {0, 0};

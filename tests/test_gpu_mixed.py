@@ -92,3 +92,42 @@ def test_mixed_rejects_unsupported_block():
         cqr.qr_mixed(Y, 100)
     with pytest.raises(cqr.CqrError):
         cqr.qr_mixed(to_dev(inputs.diag_dominant(512, seed=1)), 272)
+
+
+U_FP8 = 2.0 ** -4
+
+
+@pytest.mark.parametrize("n,b", [(512, 64), (1000, 256), (2048, 256)])
+def test_fp8_factor_backward_error(n, b):
+    """FP8 (E4M3, per-column power-of-two scales) projections/updates: the
+    factors reconstruct Y to a small multiple of u = 2^-4 and stay close to
+    orthonormal; the triangle is exact upper with a positive diagonal."""
+    Y = inputs.diag_dominant(n, seed=n + 1)
+    Q, R, info = cqr.qr_mixed(to_dev(Y), b, prec=cqr.PREC_FP8)
+    torch.cuda.synchronize()
+    assert info == 0
+    Qh, Rh = _host32(Q), _host32(R)
+    assert np.array_equal(np.tril(Rh, -1), np.zeros_like(Rh))
+    assert (np.diag(Rh) > 0).all()
+    rec = np.linalg.norm(Y - Qh @ Rh) / np.linalg.norm(Y)
+    orth = np.abs(Qh.T @ Qh - np.eye(n)).max()
+    assert rec < 2 * U_FP8, rec
+    assert orth < 4 * U_FP8, orth
+
+
+@pytest.mark.parametrize("n,b", [(512, 64), (4096, 256)])
+def test_fp8_ir_solve_reaches_fp64_residual(n, b):
+    Y = inputs.diag_dominant(n, seed=17 + n)
+    rhs = inputs.uniform_vector(n, seed=18 + n)
+    Yd = to_dev(Y)
+    Q, R, info = cqr.qr_mixed(Yd, b, prec=cqr.PREC_FP8)
+    assert info == 0
+    x, iters, res = cqr.solve_ir(Yd, Q, R, torch.from_numpy(rhs).cuda(), maxiter=50, tol=16.0)
+    torch.cuda.synchronize()
+    xh = x.cpu().numpy()
+    assert res < 16 and 1 <= iters < 50
+    assert hpl_ratio(Y, xh, rhs) < 16
+    ref = oracle.cgs_qr(Y, 64)
+    xo, rc = oracle.qr_solve(ref["Q"], ref["R"], rhs)
+    assert rc == 0
+    assert np.abs(xh - xo).max() < 16 * np.linalg.cond(Y) * n * EPS * np.abs(xo).max()
