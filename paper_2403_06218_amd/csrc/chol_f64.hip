@@ -64,11 +64,16 @@ chol_inv_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __rest
     const int c0 = 16 * p;
     if (p > 0) {
       for (int t = p + wave; t < P; t += 4) {
-        chol_d4 acc = {0.0, 0.0, 0.0, 0.0};
-        for (int k0 = 0; k0 < c0; k0 += 4)
-          acc = mma64(sA[(16 * t + li) * kCLD + k0 + lg], sA[(c0 + li) * kCLD + k0 + lg], acc);
+        // Four independent accumulators (k0 mod 16) shorten the dependent chain.
+        chol_d4 acc[4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+        for (int k0 = 0; k0 < c0; k0 += 16) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) sA[(16 * t + lg + 4 * v) * kCLD + c0 + li] -= acc[v];
+          for (int u = 0; u < 4; ++u)
+            acc[u] = mma64(sA[(16 * t + li) * kCLD + k0 + 4 * u + lg], sA[(c0 + li) * kCLD + k0 + 4 * u + lg], acc[u]);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          sA[(16 * t + lg + 4 * v) * kCLD + c0 + li] -= (acc[0][v] + acc[1][v]) + (acc[2][v] + acc[3][v]);
       }
       __syncthreads();
     }
@@ -82,37 +87,29 @@ chol_inv_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __rest
       if (lane == 0 && !ok) bad = 1;
       if (lane < 16) {
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          if (j < lane) {
-            sA[(c0 + lane) * kCLD + c0 + j] = a[j];
-            sT[lane * kCLD + j] = a[j] * linv;  // M(i, j) = L(i, j) / L(i, i)
-          }
-        }
+        for (int j = 0; j < 16; ++j)
+          if (j < lane) sA[(c0 + lane) * kCLD + c0 + j] = a[j];
         sA[(c0 + lane) * kCLD + c0 + lane] = lii;
         sD[c0 + lane] = linv;
       }
-      // The wave's LDS writes complete before its lanes read each other's.
-      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-      // Lane j < 16 forms column j of X_pp = L_pp^{-1}: with M = D^{-1} L
-      // (row i scaled by 1 / L_ii, unit diagonal), X = M^{-1} D^{-1} and
-      // column j of M^{-1} is v_j = 1, v_i = -sum_{j <= k < i} M_ik v_k.
-      // Two partial sums halve the dependent chain.
-      double x[16];
+      // X_pp = L_pp^{-1} in registers: with M = D^{-1} L (row i scaled by
+      // 1 / L_ii, unit diagonal), X = M^{-1} D^{-1}.  Lane i owns row i of
+      // M^{-1}, formed right-looking from the identity: at step k row k is
+      // final and is broadcast, and every row i > k subtracts M_ik times it.
+      double xr[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        double s0 = 0.0, s1 = 0.0;
+      for (int j = 0; j < 16; ++j) xr[j] = (j == lane) ? 1.0 : 0.0;
 #pragma unroll
-        for (int k = 0; k < i; k += 2) {
-          s0 += sT[i * kCLD + k] * x[k];
-          if (k + 1 < i) s1 += sT[i * kCLD + k + 1] * x[k + 1];
-        }
-        x[i] = (i == lane) ? 1.0 : ((i > lane) ? -(s0 + s1) : 0.0);
+      for (int k = 0; k < 15; ++k) {
+        const double mik = (lane > k) ? a[k] * linv : 0.0;
+#pragma unroll
+        for (int j = 0; j <= k; ++j) xr[j] -= mik * wave_bcast(xr[j], k);
       }
-      if (lane < 16) {
-        const double dj = linv;  // column j of X = (column j of M^{-1}) / L_jj
+      // X(i, j) = (M^{-1})_ij / L_jj, stored transposed above the diagonal.
 #pragma unroll
-        for (int i = 0; i < 16; ++i)
-          if (i > lane) sA[(c0 + lane) * kCLD + c0 + i] = x[i] * dj;
+      for (int j = 0; j < 16; ++j) {
+        const double djinv = wave_bcast(linv, j);
+        if (lane < 16 && j < lane) sA[(c0 + j) * kCLD + c0 + lane] = xr[j] * djinv;
       }
     }
     __syncthreads();
@@ -135,15 +132,19 @@ chol_inv_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __rest
     const int r0 = 16 * i;
     // T = L[r0:r0+16, 0:r0] X[0:r0, 0:r0] (X lower: start each tile's sum at its diagonal).
     for (int jt = wave; jt < i; jt += 4) {
-      chol_d4 acc = {0.0, 0.0, 0.0, 0.0};
+      chol_d4 acc[4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
       const int j = 16 * jt + li;
-      for (int k0 = 16 * jt; k0 < r0; k0 += 4) {
-        const int k = k0 + lg;
-        const double bx = (k > j) ? sA[j * kCLD + k] : ((k == j) ? sD[k] : 0.0);
-        acc = mma64(sA[(r0 + li) * kCLD + k], bx, acc);
+      for (int k0 = 16 * jt; k0 < r0; k0 += 16) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 + 4 * u + lg;
+          const double bx = (k > j) ? sA[j * kCLD + k] : ((k == j) ? sD[k] : 0.0);
+          acc[u] = mma64(sA[(r0 + li) * kCLD + k], bx, acc[u]);
+        }
       }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) sT[(lg + 4 * v) * kCLD + 16 * jt + li] = acc[v];
+      for (int v = 0; v < 4; ++v)
+        sT[(lg + 4 * v) * kCLD + 16 * jt + li] = (acc[0][v] + acc[1][v]) + (acc[2][v] + acc[3][v]);
     }
     __syncthreads();
     // X[r0:r0+16, 0:r0] = -X_ii T, stored transposed above the diagonal.
