@@ -215,25 +215,15 @@ gemv_t_kernel(int64_t n, const double* __restrict__ Q, int64_t ldq, const double
 constexpr int kTrsvNB = 64;
 
 // Back substitution on the diagonal block R[i0:i0+nb, i0:i0+nb] of upper R:
-// y[i0:i0+nb] := R_blk^{-1} y[i0:i0+nb].  One 64-thread workgroup.
+// y[i0:i0+nb] := R_blk^{-1} y[i0:i0+nb].  One wave, rows in registers.
 __global__ void __launch_bounds__(kTrsvNB)
 trsv_diag_kernel(int64_t i0, int nb, const double* __restrict__ R, int64_t ldr, double* __restrict__ y) {
-  __shared__ double sR[kTrsvNB][kTrsvNB + 1];
-  __shared__ double xs;
-  const int t = threadIdx.x;
-  for (int c = 0; c < nb; ++c)
-    if (t < nb) sR[t][c] = R[(i0 + t) + (i0 + c) * ldr];
+  const int t = threadIdx.x;  // one wave; lane t holds row i0 + t of the block
+  double u[kTrsvNB];
+#pragma unroll
+  for (int c = 0; c < kTrsvNB; ++c) u[c] = (t < nb && c < nb && c >= t) ? R[(i0 + t) + (i0 + c) * ldr] : 0.0;
   double v = (t < nb) ? y[i0 + t] : 0.0;
-  __syncthreads();
-  for (int i = nb - 1; i >= 0; --i) {
-    if (t == i) {
-      v = v / sR[i][i];
-      xs = v;
-    }
-    __syncthreads();
-    if (t < i) v -= sR[t][i] * xs;
-    __syncthreads();
-  }
+  v = wave_back_subst<double, double, kTrsvNB>(u, v, nb, t);
   if (t < nb) y[i0 + t] = v;
 }
 

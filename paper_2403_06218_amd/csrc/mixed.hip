@@ -135,7 +135,8 @@ __device__ __forceinline__ float pow2_scale(double m) {
 }
 
 // cmax[j] = max_i |src(i, j) * rowscale[i]| (rowscale may be NULL); one
-// workgroup per column.
+// workgroup per column, 8 loads in flight per thread.  Maxima are exact, so
+// the order of the reduction does not matter.
 __global__ void __launch_bounds__(256)
 colmax_kernel(int64_t rows, const double* __restrict__ src, int64_t lds, const float* __restrict__ rowscale,
               double* __restrict__ cmax, const int* __restrict__ gate) {
@@ -144,10 +145,15 @@ colmax_kernel(int64_t rows, const double* __restrict__ src, int64_t lds, const f
   const int j = blockIdx.x, t = threadIdx.x;
   const double* col = src + (int64_t)j * lds;
   double m = 0.0;
-  for (int64_t i = t; i < rows; i += 256) {
-    const double v = fabs(col[i] * (rowscale ? (double)rowscale[i] : 1.0));
-    m = v > m ? v : m;
+  int64_t i0 = t;
+  for (; i0 + 7 * 256 < rows; i0 += 8 * 256) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = col[i0 + u * 256] * (rowscale ? (double)rowscale[i0 + u * 256] : 1.0);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) m = fmax(m, fabs(v[u]));
   }
+  for (; i0 < rows; i0 += 256) m = fmax(m, fabs(col[i0] * (rowscale ? (double)rowscale[i0] : 1.0)));
   red[t] = m;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {

@@ -56,4 +56,26 @@ __device__ __forceinline__ bool wave_chol(T (&a)[WP], T& lii, T& linv, int lane)
   return ok;
 }
 
+// Back substitution U x = y for an upper triangular nb x nb block (nb <= NB
+// <= 64) held by one wave: lane i < nb holds row i in u[0..NB) and y_i.
+// Returns x_i in lane i.  The reciprocals of the diagonal are formed first,
+// in parallel, so each step's dependent chain is two broadcasts, a multiply
+// and a fused multiply-add.
+// The row may be stored in a narrower type U (converted exactly to T).
+template <typename T, typename U, int NB>
+__device__ __forceinline__ T wave_back_subst(const U (&u)[NB], T y, int nb, int lane) {
+  T d = T(1);
+#pragma unroll
+  for (int c = 0; c < NB; ++c) d = (lane == c) ? (T)u[c] : d;
+  const T inv = T(1) / d;
+#pragma unroll
+  for (int c = NB - 1; c >= 0; --c) {
+    if (c < nb) {
+      const T xc = wave_bcast(y, c) * wave_bcast(inv, c);
+      y = (lane == c) ? xc : ((lane < c) ? y - (T)u[c] * xc : y);
+    }
+  }
+  return y;
+}
+
 }  // namespace cqr
