@@ -348,7 +348,7 @@ def bench_fp64(args, torch, cqr, costmodel, inputs):
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    swork = torch.empty(max(256, 8 * n), dtype=torch.uint8, device=dev)
+    swork = torch.empty(cqr.solve_workspace_size(n), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 
     def step(i):

@@ -23,7 +23,7 @@ FLAG_ZERO_COL = 2
 PREC_BF16 = 1
 PREC_FP8 = 2
 
-__all__ = ["colmajor", "workspace_size", "qr", "orth", "orth_against", "solve", "qr_mixed", "solve_ir",
+__all__ = ["colmajor", "workspace_size", "qr", "orth", "orth_against", "solve", "solve_workspace_size", "qr_mixed", "solve_ir",
            "synth_uniform",
            "prof_enable", "prof_reset", "prof_query", "prof_names", "CqrError", "version"]
 
@@ -129,14 +129,19 @@ def orth_against(Q: torch.Tensor, P: torch.Tensor, H: torch.Tensor | None = None
     return Q, H, R, int(info.value)
 
 
+def solve_workspace_size(n: int) -> int:
+    """Bytes of device workspace solve() needs for order n."""
+    nb = ctypes.c_size_t(0)
+    _native.check(_native.lib().cqr_solve_workspace_size(n, ctypes.byref(nb)), "cqr_solve_workspace_size")
+    return int(nb.value)
+
+
 def solve(Q: torch.Tensor, R: torch.Tensor, rhs: torch.Tensor, work: torch.Tensor | None = None) -> torch.Tensor:
     """x = R^{-1} Q^T rhs (asynchronous on the current stream).  rhs is not modified."""
     n = Q.shape[0]
     x = rhs.clone().contiguous()
-    nb = ctypes.c_size_t(0)
-    _native.check(_native.lib().cqr_solve_workspace_size(n, ctypes.byref(nb)), "cqr_solve_workspace_size")
     if work is None:
-        work = _workspace(int(nb.value), Q.device)
+        work = _workspace(solve_workspace_size(n), Q.device)
     rc = _native.lib().cqr_solve(n, _ptr(Q), _ld(Q, "Q"), _ptr(R), _ld(R, "R"), _ptr(x), _ptr(work), work.numel(),
                                  _stream())
     _native.check(rc, "cqr_solve")

@@ -42,20 +42,20 @@ chol_inv_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __rest
   const int li = lane & 15, lg = lane >> 4;
   const int nb = (b + 15) & ~15, P = nb >> 4;
   if (tid == 0) bad = 0;
-  // Loads in batches of 16 per thread, so that their latencies overlap.
-  for (int e0 = tid; e0 < nb * nb; e0 += 256 * 16) {
-    double v[16];
+  // Thread t loads row t % 128 of columns t / 128, +2, +4, ...: all of its
+  // loads are issued before the first LDS store, so their latencies overlap.
+  const int ri = tid & (kCB - 1), rj = tid >> 7;
+  {
+    double v[kCB / 2];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int e = e0 + 256 * u;
-      const int j = e / nb, i = e - j * nb;
-      v[u] = (e < nb * nb && i < b && j < b) ? W[i + (int64_t)j * ldw] : (i == j ? 1.0 : 0.0);
+    for (int u = 0; u < kCB / 2; ++u) {
+      const int j = rj + 2 * u;
+      v[u] = (ri < b && j < b) ? W[ri + (int64_t)j * ldw] : (ri == j ? 1.0 : 0.0);
     }
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int e = e0 + 256 * u;
-      const int j = e / nb, i = e - j * nb;
-      if (e < nb * nb) sA[i * kCLD + j] = v[u];
+    for (int u = 0; u < kCB / 2; ++u) {
+      const int j = rj + 2 * u;
+      if (ri < nb && j < nb) sA[ri * kCLD + j] = v[u];
     }
   }
   __syncthreads();
@@ -162,11 +162,15 @@ chol_inv_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __rest
     __syncthreads();
   }
 
-  // LT(j, i) = L(i, j) and XT(j, i) = X(i, j), both upper triangular, ld ldo.
-  for (int e = tid; e < b * b; e += 256) {
-    const int i = e / b, j = e - i * b;
-    LT[j + (int64_t)i * ldo] = (i >= j) ? sA[i * kCLD + j] : 0.0;
-    XT[j + (int64_t)i * ldo] = (i > j) ? sA[j * kCLD + i] : ((i == j) ? sD[i] : 0.0);
+  // LT(j, i) = L(i, j) and XT(j, i) = X(i, j), both upper triangular, ld ldo:
+  // thread t writes entry t % 128 of output columns t / 128, +2, +4, ...
+#pragma unroll 16
+  for (int u = 0; u < kCB / 2; ++u) {
+    const int i = rj + 2 * u, j = ri;
+    if (i < b && j < b) {
+      LT[j + (int64_t)i * ldo] = (i >= j) ? sA[i * kCLD + j] : 0.0;
+      XT[j + (int64_t)i * ldo] = (i > j) ? sA[j * kCLD + i] : ((i == j) ? sD[i] : 0.0);
+    }
   }
   __syncthreads();
   if (tid == 0 && bad) {
@@ -210,34 +214,6 @@ gemv_t_kernel(int64_t n, const double* __restrict__ Q, int64_t ldq, const double
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
   if (lane == 0) y[j] = acc;
-}
-
-constexpr int kTrsvNB = 64;
-
-// Back substitution on the diagonal block R[i0:i0+nb, i0:i0+nb] of upper R:
-// y[i0:i0+nb] := R_blk^{-1} y[i0:i0+nb].  One wave, rows in registers.
-__global__ void __launch_bounds__(kTrsvNB)
-trsv_diag_kernel(int64_t i0, int nb, const double* __restrict__ R, int64_t ldr, double* __restrict__ y) {
-  const int t = threadIdx.x;  // one wave; lane t holds row i0 + t of the block
-  double u[kTrsvNB];
-#pragma unroll
-  for (int c = 0; c < kTrsvNB; ++c) u[c] = (t < nb && c < nb && c >= t) ? R[(i0 + t) + (i0 + c) * ldr] : 0.0;
-  double v = (t < nb) ? y[i0 + t] : 0.0;
-  v = wave_back_subst<double, double, kTrsvNB>(u, v, nb, t);
-  if (t < nb) y[i0 + t] = v;
-}
-
-// y[0:i0] -= R[0:i0, i0:i0+nb] y[i0:i0+nb].
-__global__ void __launch_bounds__(256)
-trsv_update_kernel(int64_t i0, int nb, const double* __restrict__ R, int64_t ldr, double* __restrict__ y) {
-  __shared__ double xs[kTrsvNB];
-  if (threadIdx.x < nb) xs[threadIdx.x] = y[i0 + threadIdx.x];
-  __syncthreads();
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= i0) return;
-  double acc = 0.0;
-  for (int c = 0; c < nb; ++c) acc += R[r + (i0 + c) * ldr] * xs[c];
-  y[r] -= acc;
 }
 
 unsigned grid_for(int64_t total) {
@@ -329,23 +305,5 @@ hipError_t gemv_t(int64_t n, const double* Q, int64_t ldq, const double* x, doub
   return e;
 }
 
-hipError_t trsv_upper(int64_t n, const double* R, int64_t ldr, double* y, hipStream_t s) {
-  for (int64_t i0 = ((n - 1) / kTrsvNB) * kTrsvNB; i0 >= 0 && n > 0; i0 -= kTrsvNB) {
-    const int nb = (int)((n - i0) < kTrsvNB ? (n - i0) : kTrsvNB);
-    int slot = prof_begin(s);
-    hipLaunchKernelGGL(trsv_diag_kernel, dim3(1), dim3(kTrsvNB), 0, s, i0, nb, R, ldr, y);
-    hipError_t e = hipGetLastError();
-    prof_end(slot, ROLE_TRSV_DIAG, s, (double)nb * nb, 8.0 * (double)nb * nb / 2.0);
-    if (e != hipSuccess) return e;
-    if (i0 > 0) {
-      slot = prof_begin(s);
-      hipLaunchKernelGGL(trsv_update_kernel, dim3((unsigned)((i0 + 255) / 256)), dim3(256), 0, s, i0, nb, R, ldr, y);
-      e = hipGetLastError();
-      prof_end(slot, ROLE_TRSV_UPD, s, 2.0 * (double)i0 * nb, 8.0 * (double)i0 * nb);
-      if (e != hipSuccess) return e;
-    }
-  }
-  return hipSuccess;
-}
 
 }  // namespace cqr

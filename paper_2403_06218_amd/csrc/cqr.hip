@@ -56,7 +56,7 @@ hipEvent_t pool_get() {
 }
 
 const char* const kRoleNames[ROLE_COUNT] = {"proj", "update", "gram", "trsm", "small", "reduce",
-                                            "chol", "copy", "gemv", "trsv_diag", "trsv_update",
+                                            "chol", "copy", "gemv", "trsv_inv", "trsv",
                                             "batch", "batch_setup", "adjoint"};
 }  // namespace
 
@@ -400,7 +400,7 @@ int cqr_orth_against(int64_t q, int64_t b, int64_t s, double* Q, int64_t ldq, co
 int cqr_solve_workspace_size(int64_t n, size_t* bytes) {
   if (n < 0) return -1;
   if (!bytes) return -2;
-  *bytes = align256((size_t)(n > 0 ? n : 1) * sizeof(double));
+  *bytes = align256((size_t)(n > 0 ? n : 1) * sizeof(double)) + trsv_workspace_bytes(n);
   return CQR_OK;
 }
 
@@ -413,11 +413,15 @@ int cqr_solve(int64_t n, const double* Q, int64_t ldq, const double* R, int64_t 
   if (ldr < (n > 1 ? n : 1)) return -5;
   if (!x && n > 0) return -6;
   if (n == 0) return CQR_OK;
-  if (!work || work_bytes < (size_t)n * sizeof(double)) return CQR_ERR_WORKSPACE;
+  size_t need = 0;
+  cqr_solve_workspace_size(n, &need);
+  if (!work || work_bytes < need) return CQR_ERR_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
   double* y = (double*)work;
+  void* tw = (char*)work + align256((size_t)n * sizeof(double));
   CQR_TRY(gemv_t(n, Q, ldq, x, y, st));
-  CQR_TRY(trsv_upper(n, R, ldr, y, st));
+  CQR_TRY(trsv_prepare(n, false, R, ldr, tw, st));
+  CQR_TRY(trsv_solve(n, false, R, ldr, tw, y, 0, st));
   CQR_TRY(copy_matrix(n, 1, y, n, x, n, nullptr, st));
   return CQR_OK;
 }

@@ -475,11 +475,14 @@ Plan plan_gemm(bool ta, int64_t M, int64_t N, int64_t K, const double* A, int64_
   p.mt = p.nt = 0;
   // Skinny shapes (block widths up to 32, as in the tall orthogonalisation):
   // exact-width tiles, and for A^T B enough splits of the long reduction for
-  // about 2048 workgroups.
+  // about 2048 workgroups.  Small products that cannot split their reduction
+  // (at most 256 x 256: the block Cholesky composition, R_jj = Lb^T L^T) take
+  // 32 x 32 tiles, so that 16-64 workgroups share the work instead of 1-4.
   if (p.dma) {
     if (ta && N <= 16 && M <= 64) { p.mt = 16; p.nt = 16; }
     else if (ta && M <= 32 && N <= 32) { p.mt = 32; p.nt = 32; }
     else if (!ta && N <= 16 && M > 64) { p.mt = 128; p.nt = 16; }
+    else if (!(allow_split && ta) && M <= 256 && N <= 256) { p.mt = 32; p.nt = 32; }
   }
   if (p.mt != 0) {
     if (allow_split && ta) {
@@ -568,10 +571,8 @@ hipError_t launch(const Plan& p, int64_t M, int64_t N, int64_t K, double alpha, 
       if constexpr (TA)
         return launch_dma<ROLE, TA, 16, 16, 3, 8, 1, 1>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
     }
-    if (p.mt == 32) {
-      if constexpr (TA)
-        return launch_dma<ROLE, TA, 32, 32, 3, 4>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
-    }
+    if (p.mt == 32)
+      return launch_dma<ROLE, TA, 32, 32, 3, 4>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
     if (p.nt == 16) {
       if constexpr (!TA)
         return launch_dma<ROLE, TA, 128, 16, 3, 4, 2, 1>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);

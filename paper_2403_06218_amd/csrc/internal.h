@@ -20,8 +20,8 @@ enum Role : int {
   ROLE_CHOL,        // W = L L^T and L^{-1}  (Alg. 4 S2/S5, 5 S4/S9)
   ROLE_COPY,        // block save / restore for the breakdown fallback
   ROLE_GEMV,        // solve: c = Q^T rhs
-  ROLE_TRSV_DIAG,   // solve: diagonal-block back substitution
-  ROLE_TRSV_UPD,    // solve: off-diagonal update
+  ROLE_TRSV_INV,    // solve: inverses of the 64 x 64 diagonal blocks of R
+  ROLE_TRSV,        // solve: back substitution R x = c, one launch
   ROLE_BATCH,       // batched form: whole factorisation + solve, one workgroup per matrix
   ROLE_BATCH_SETUP, // batched form: size sort and bucket boundaries
   ROLE_ADJOINT,     // adjoint of the solve
@@ -85,6 +85,17 @@ hipError_t zero_matrix(int64_t rows, int64_t cols, double* X, int64_t ldx, hipSt
 
 // Solve kernels.
 hipError_t gemv_t(int64_t n, const double* Q, int64_t ldq, const double* x, double* y, hipStream_t s);
-hipError_t trsv_upper(int64_t n, const double* R, int64_t ldr, double* y, hipStream_t s);
+
+// Back substitution R x = c (R n x n upper triangular, FP64 or FP32 entries;
+// c and x FP64, in place in y).  trsv_prepare forms the inverses of R's
+// 64 x 64 diagonal blocks in `work` (trsv_workspace_bytes(n)) and clears its
+// counters; then trsv_solve calls number seq = 0, 1, 2, ... of that sequence
+// each solve one right-hand side with the same R.  *trsv_error_word(n, work)
+// is nonzero if a wait was abandoned (the result is then not valid).
+size_t trsv_workspace_bytes(int64_t n);
+hipError_t trsv_prepare(int64_t n, bool f32, const void* R, int64_t ldr, void* work, hipStream_t s);
+hipError_t trsv_solve(int64_t n, bool f32, const void* R, int64_t ldr, void* work, double* y, int64_t seq,
+                      hipStream_t s);
+const unsigned* trsv_error_word(int64_t n, const void* work);
 
 }  // namespace cqr

@@ -349,69 +349,6 @@ gemv_t_f32_kernel(int64_t n, const float* __restrict__ Q, int64_t ldq, const dou
   if (lane == 0) y[j] = acc;
 }
 
-constexpr int kNB = 64;
-
-// One launch per 64-row block I (last first): rows of blocks above subtract
-// R[rows, I] x_I, and the workgroup that owns block I-1 then back-substitutes
-// its diagonal block.  x_I is final when the launch for block I starts.
-__global__ void __launch_bounds__(kNB)
-trsv_f32_step_kernel(int64_t n, const float* __restrict__ R, int64_t ldr, double* __restrict__ y, int64_t i0) {
-  // blockIdx.x covers rows [blockIdx.x * 64, +64) of the region [0, i0).
-  __shared__ double xs[kNB];
-  __shared__ double sR[kNB][kNB + 1];
-  const int t = threadIdx.x;
-  const int64_t nb = (n - i0 < kNB) ? n - i0 : kNB;  // width of block I (already solved)
-  if (t < nb) xs[t] = y[i0 + t];
-  __syncthreads();
-  const int64_t r0 = (int64_t)blockIdx.x * kNB;
-  const int64_t row = r0 + t;
-  double v = 0.0;
-  if (row < i0) {
-    double acc = 0.0;
-    for (int c = 0; c < nb; ++c) acc += (double)R[row + (i0 + c) * ldr] * xs[c];
-    v = y[row] - acc;
-  }
-  // The last workgroup holds block I-1 = rows [i0 - 64, i0): solve it.
-  if (r0 + kNB == i0) {
-    for (int c = 0; c < kNB; ++c) sR[t][c] = (double)R[(r0 + t) + (r0 + c) * ldr];
-    __syncthreads();
-    __shared__ double xv;
-    for (int i = kNB - 1; i >= 0; --i) {
-      if (t == i) {
-        v = v / sR[i][i];
-        xv = v;
-      }
-      __syncthreads();
-      if (t < i) v -= sR[t][i] * xv;
-      __syncthreads();
-    }
-  }
-  if (row < i0) y[row] = v;
-}
-
-// Back substitution of the last (possibly partial) block [i0, n) alone.
-__global__ void __launch_bounds__(kNB)
-trsv_f32_last_kernel(int64_t n, const float* __restrict__ R, int64_t ldr, double* __restrict__ y, int64_t i0) {
-  __shared__ double sR[kNB][kNB + 1];
-  __shared__ double xv;
-  const int t = threadIdx.x;
-  const int nb = (int)(n - i0);
-  for (int c = 0; c < nb; ++c)
-    if (t < nb) sR[t][c] = (double)R[(i0 + t) + (i0 + c) * ldr];
-  double v = (t < nb) ? y[i0 + t] : 0.0;
-  __syncthreads();
-  for (int i = nb - 1; i >= 0; --i) {
-    if (t == i) {
-      v = v / sR[i][i];
-      xv = v;
-    }
-    __syncthreads();
-    if (t < i) v -= sR[t][i] * xv;
-    __syncthreads();
-  }
-  if (t < nb) y[i0 + t] = v;
-}
-
 __global__ void __launch_bounds__(256) axpy_kernel(int64_t n, const double* __restrict__ d, double* __restrict__ x) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) x[i] += d[i];
@@ -590,7 +527,8 @@ int cqr_solve_ir_workspace_size(int64_t n, size_t* bytes) {
   if (n < 0) return -1;
   if (!bytes) return -2;
   const int64_t nchunk = 16;
-  *bytes = a256((size_t)(nchunk + 4) * (size_t)(n > 0 ? n : 1) * 8) + a256((size_t)((n + 255) / 256 + 8) * 8);
+  *bytes = a256((size_t)(nchunk + 4) * (size_t)(n > 0 ? n : 1) * 8) + a256((size_t)((n + 255) / 256 + 8) * 8) +
+           trsv_workspace_bytes(n);
   return CQR_OK;
 }
 
@@ -623,6 +561,9 @@ int cqr_solve_ir(int64_t n, const double* Y, int64_t ldy, const float* Q, int64_
   double* bm = (double*)((char*)work + a256((size_t)(nchunk + 4) * n * 8));  // block maxima, then scalars
   const int64_t nblk = (n + 255) / 256;
   double* scal = bm + nblk;                     // [0] |Y|_inf [1] |r|_inf [2] |x|_inf
+  void* tw = (char*)work + a256((size_t)(nchunk + 4) * n * 8) + a256((size_t)(nblk + 8) * 8);
+  const unsigned* terr = trsv_error_word(n, tw);
+  MX_TRY(trsv_prepare(n, true, R, ldr, tw, st));
   const dim3 gpart((unsigned)nblk, (unsigned)nchunk);
   // ||Y||_inf once.
   hipLaunchKernelGGL(gemv_n_part_kernel<true>, gpart, dim3(256), 0, st, n, Y, ldy, (const double*)nullptr, chunk, part);
@@ -640,13 +581,7 @@ int cqr_solve_ir(int64_t n, const double* Y, int64_t ldy, const float* Q, int64_
     // d = R^{-1} Q^T r
     hipLaunchKernelGGL(gemv_t_f32_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, n, Q, ldq, r, c);
     MX_TRY(hipGetLastError());
-    const int64_t ilast = ((n - 1) / kNB) * kNB;
-    hipLaunchKernelGGL(trsv_f32_last_kernel, dim3(1), dim3(kNB), 0, st, n, R, ldr, c, ilast);
-    MX_TRY(hipGetLastError());
-    for (int64_t i0 = ilast; i0 > 0; i0 -= kNB) {
-      hipLaunchKernelGGL(trsv_f32_step_kernel, dim3((unsigned)(i0 / kNB)), dim3(kNB), 0, st, n, R, ldr, c, i0);
-      MX_TRY(hipGetLastError());
-    }
+    MX_TRY(trsv_solve(n, true, R, ldr, tw, c, it - 1, st));
     hipLaunchKernelGGL(axpy_kernel, dim3((unsigned)nblk), dim3(256), 0, st, n, c, x);
     MX_TRY(hipGetLastError());
     // r = rhs - Y x, ||r||_inf, ||x||_inf
@@ -659,8 +594,11 @@ int cqr_solve_ir(int64_t n, const double* Y, int64_t ldy, const float* Q, int64_
     hipLaunchKernelGGL(max_kernel, dim3(1), dim3(256), 0, st, n, x, scal + 2);
     MX_TRY(hipGetLastError());
     double h[3];
+    unsigned herr = 0;
     MX_TRY(hipMemcpyAsync(h, scal, sizeof(h), hipMemcpyDeviceToHost, st));
+    MX_TRY(hipMemcpyAsync(&herr, terr, sizeof(herr), hipMemcpyDeviceToHost, st));
     MX_TRY(hipStreamSynchronize(st));
+    if (herr != 0) return CQR_ERR_HIP_BASE - (int)hipErrorLaunchTimeOut;
     const double res = h[1] / (h[0] * h[2] * (double)n * eps);
     if (iters) *iters = it;
     if (scaled_resid) *scaled_resid = res;

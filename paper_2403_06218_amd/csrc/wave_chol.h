@@ -1,6 +1,7 @@
 // Cholesky factorisation of a small SPD block (WP <= 32) held by one wave:
 // lane i < WP owns row i.  Shared by the single-matrix factor kernel (its
-// 16 x 16 diagonal blocks) and the batched form (its block Grams).
+// 16 x 16 diagonal blocks) and the batched form (its block Grams); and the
+// wave broadcast used by the solve kernels.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -54,28 +55,6 @@ __device__ __forceinline__ bool wave_chol(T (&a)[WP], T& lii, T& linv, int lane)
 #pragma unroll
   for (int j = 0; j < WP; ++j) a[j] *= wave_bcast(s, j);
   return ok;
-}
-
-// Back substitution U x = y for an upper triangular nb x nb block (nb <= NB
-// <= 64) held by one wave: lane i < nb holds row i in u[0..NB) and y_i.
-// Returns x_i in lane i.  The reciprocals of the diagonal are formed first,
-// in parallel, so each step's dependent chain is two broadcasts, a multiply
-// and a fused multiply-add.
-// The row may be stored in a narrower type U (converted exactly to T).
-template <typename T, typename U, int NB>
-__device__ __forceinline__ T wave_back_subst(const U (&u)[NB], T y, int nb, int lane) {
-  T d = T(1);
-#pragma unroll
-  for (int c = 0; c < NB; ++c) d = (lane == c) ? (T)u[c] : d;
-  const T inv = T(1) / d;
-#pragma unroll
-  for (int c = NB - 1; c >= 0; --c) {
-    if (c < nb) {
-      const T xc = wave_bcast(y, c) * wave_bcast(inv, c);
-      y = (lane == c) ? xc : ((lane < c) ? y - (T)u[c] * xc : y);
-    }
-  }
-  return y;
 }
 
 }  // namespace cqr
