@@ -112,8 +112,13 @@ int cqr_solve_workspace_size(int64_t n, size_t* bytes);
  * x = R^{-1} (Q^T rhs) -- a matrix-vector product then back substitution.
  * (The paper does not solve systems; this is the factorisation's use.)
  *   x        in: rhs (length n); out: the solution.
+ *   work     device, cqr_solve_workspace_size(n) bytes: Q^T rhs, the FP64
+ *            inverses of R's 64 x 64 diagonal blocks and the counters of the
+ *            one-launch substitution (cleared by the call itself).  Calls that
+ *            share a workspace must not overlap.
  * A zero diagonal entry of R (a dependent column) yields Inf/NaN entries.
- * Asynchronous: enqueues the work on `stream` and returns.
+ * Asynchronous: enqueues the work on `stream` and returns (capturable in a
+ * hipGraph: kernels only).
  */
 int cqr_solve(int64_t n, const double* Q, int64_t ldq, const double* R, int64_t ldr, double* x, void* work,
               size_t work_bytes, void* stream);
@@ -145,7 +150,9 @@ int cqr_factor_mixed(int64_t q, int64_t r, int64_t b, int prec, const double* Y,
  * ||r||_inf / (||Y||_inf ||x||_inf n eps) < tol or after maxiter updates.
  *   x        out (device, FP64, length n).
  *   iters, scaled_resid   host, may be NULL: updates done, final residual.
- * Synchronises the stream once per iteration.
+ * Synchronises the stream once per iteration.  Returns
+ * -1000 - hipErrorLaunchTimeOut if the back substitution ever abandoned a
+ * wait for a finished block (a bounded wait; x is then not valid).
  */
 int cqr_solve_ir_workspace_size(int64_t n, size_t* bytes);
 int cqr_solve_ir(int64_t n, const double* Y, int64_t ldy, const float* Q, int64_t ldq, const float* R, int64_t ldr,
