@@ -22,14 +22,17 @@ constexpr int kCLD = kCB + 1;  // LDS row stride (odd: column walks are conflict
 // holds X^T for X = L^{-1}, and sD the diagonal of X (1 / L_ii).  Rows and
 // columns b .. 16 ceil(b/16) - 1 are padded with the identity.
 //
-// Panel p (columns c0 = 16p .. c0+15), left-looking:
-//   1. panel update  A[c0:, c0:c0+16] -= L[c0:, :c0] L[c0:c0+16, :c0]^T (MFMA);
-//   2. wave 0 factors the 16 x 16 diagonal block in registers (readlane
-//      broadcasts) and forms its inverse X_pp column by column;
-//   3. the rows below take L = A X_pp^T (MFMA).
-// Then X block row by block row: X_i,0:i = -X_ii (L_i,0:i X_0:i,0:i) (MFMA).
-// A pivot that is not > 0 (NaN included) marks a breakdown; the kernel runs
-// to the end and reports it in status.
+// Panel p (columns c0 = 16p .. c0+15), left-looking, in two phases:
+//   1. wave 0 updates the diagonal tile, A[c0:c0+16, c0:c0+16] -=
+//      L[c0:c0+16, :c0] L[c0:c0+16, :c0]^T (MFMA), factors it in registers
+//      (readlane broadcasts) and forms its inverse X_pp; meanwhile waves 1-3
+//      update the tiles below it the same way and form block row p-1 of
+//      X = L^{-1}:  X_i,0:i = -X_ii (L_i,0:i X_0:i,0:i) (MFMA), one tile per
+//      wave, so that the serial diagonal work hides the rest;
+//   2. the rows below take L = A X_pp^T (MFMA).
+// The last block row of X follows the loop.  A pivot that is not > 0 (NaN
+// included) marks a breakdown; the kernel runs to the end and reports it in
+// status.
 __global__ void __launch_bounds__(256)
 chol_inv_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __restrict__ LT, double* __restrict__ XT,
                 int64_t ldo, int* status, int code, int blk) {
@@ -60,25 +63,55 @@ chol_inv_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __rest
   }
   __syncthreads();
 
+  // Tile (t, p) of the panel update: A(t, p) -= L(t, 0:p) L(p, 0:p)^T, with
+  // four independent accumulators (k0 mod 16) to shorten the dependent chain.
+  auto panel_update = [&](int t, int c0) {
+    chol_d4 acc[4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+    for (int k0 = 0; k0 < c0; k0 += 16) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        acc[u] = mma64(sA[(16 * t + li) * kCLD + k0 + 4 * u + lg], sA[(c0 + li) * kCLD + k0 + 4 * u + lg], acc[u]);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      sA[(16 * t + lg + 4 * v) * kCLD + c0 + li] -= (acc[0][v] + acc[1][v]) + (acc[2][v] + acc[3][v]);
+  };
+  // Tile jt of block row i of X (one wave): T = L[r0:r0+16, 0:r0] X[0:r0, jt]
+  // (X lower: the sum starts at the diagonal tile), then X(i, jt) = -X_ii T,
+  // stored transposed above the diagonal.  T passes through the wave's own
+  // columns of sT.
+  auto inverse_tile = [&](int i, int jt) {
+    const int r0 = 16 * i;
+    chol_d4 acc[4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+    const int j = 16 * jt + li;
+    for (int k0 = 16 * jt; k0 < r0; k0 += 16) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = k0 + 4 * u + lg;
+        const double bx = (k > j) ? sA[j * kCLD + k] : ((k == j) ? sD[k] : 0.0);
+        acc[u] = mma64(sA[(r0 + li) * kCLD + k], bx, acc[u]);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      sT[(lg + 4 * v) * kCLD + 16 * jt + li] = (acc[0][v] + acc[1][v]) + (acc[2][v] + acc[3][v]);
+    chol_d4 x = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      const int k = kk + lg;
+      const double ax = (li > k) ? sA[(r0 + k) * kCLD + r0 + li] : ((li == k) ? sD[r0 + k] : 0.0);
+      x = mma64(ax, sT[k * kCLD + 16 * jt + li], x);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sA[(16 * jt + li) * kCLD + r0 + lg + 4 * v] = -x[v];
+  };
+
   for (int p = 0; p < P; ++p) {
     const int c0 = 16 * p;
-    if (p > 0) {
-      for (int t = p + wave; t < P; t += 4) {
-        // Four independent accumulators (k0 mod 16) shorten the dependent chain.
-        chol_d4 acc[4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
-        for (int k0 = 0; k0 < c0; k0 += 16) {
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-            acc[u] = mma64(sA[(16 * t + li) * kCLD + k0 + 4 * u + lg], sA[(c0 + li) * kCLD + k0 + 4 * u + lg], acc[u]);
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          sA[(16 * t + lg + 4 * v) * kCLD + c0 + li] -= (acc[0][v] + acc[1][v]) + (acc[2][v] + acc[3][v]);
-      }
-      __syncthreads();
-    }
     if (wave == 0) {
-      // Lane i < 16 holds row i of the diagonal block.
+      if (p > 0) panel_update(p, c0);
+      // Lane i < 16 holds row i of the diagonal block (this wave's own LDS
+      // writes above are ordered before these reads).
       double a[16];
 #pragma unroll
       for (int j = 0; j < 16; ++j) a[j] = (lane < 16 && j <= lane) ? sA[(c0 + lane) * kCLD + c0 + j] : 0.0;
@@ -111,6 +144,11 @@ chol_inv_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __rest
         const double djinv = wave_bcast(linv, j);
         if (lane < 16 && j < lane) sA[(c0 + j) * kCLD + c0 + lane] = xr[j] * djinv;
       }
+    } else {
+      if (p > 0)
+        for (int t = p + wave; t < P; t += 3) panel_update(t, c0);
+      if (p >= 2)
+        for (int jt = wave - 1; jt < p - 1; jt += 3) inverse_tile(p - 1, jt);
     }
     __syncthreads();
     for (int t = p + 1 + wave; t < P; t += 4) {
@@ -127,40 +165,10 @@ chol_inv_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __rest
     }
     __syncthreads();
   }
-
-  for (int i = 1; i < P; ++i) {
-    const int r0 = 16 * i;
-    // T = L[r0:r0+16, 0:r0] X[0:r0, 0:r0] (X lower: start each tile's sum at its diagonal).
-    for (int jt = wave; jt < i; jt += 4) {
-      chol_d4 acc[4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
-      const int j = 16 * jt + li;
-      for (int k0 = 16 * jt; k0 < r0; k0 += 16) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int k = k0 + 4 * u + lg;
-          const double bx = (k > j) ? sA[j * kCLD + k] : ((k == j) ? sD[k] : 0.0);
-          acc[u] = mma64(sA[(r0 + li) * kCLD + k], bx, acc[u]);
-        }
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        sT[(lg + 4 * v) * kCLD + 16 * jt + li] = (acc[0][v] + acc[1][v]) + (acc[2][v] + acc[3][v]);
-    }
-    __syncthreads();
-    // X[r0:r0+16, 0:r0] = -X_ii T, stored transposed above the diagonal.
-    for (int jt = wave; jt < i; jt += 4) {
-      chol_d4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int kk = 0; kk < 16; kk += 4) {
-        const int k = kk + lg;
-        const double ax = (li > k) ? sA[(r0 + k) * kCLD + r0 + li] : ((li == k) ? sD[r0 + k] : 0.0);
-        acc = mma64(ax, sT[k * kCLD + 16 * jt + li], acc);
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) sA[(16 * jt + li) * kCLD + r0 + lg + 4 * v] = -acc[v];
-    }
-    __syncthreads();
-  }
+  // The last block row of X.
+  if (P >= 2)
+    for (int jt = wave; jt < P - 1; jt += 4) inverse_tile(P - 1, jt);
+  __syncthreads();
 
   // LT(j, i) = L(i, j) and XT(j, i) = X(i, j), both upper triangular, ld ldo:
   // thread t writes entry t % 128 of output columns t / 128, +2, +4, ...
