@@ -18,7 +18,7 @@ HIP_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared", 
              "-I" + os.path.join(ROOT, "include")]
 
 LIBS = {
-    "libcqr.so": ["cqr.hip", "gemm_f64.hip", "chol_f64.hip", "gemm_bf16.hip", "mixed.hip", "batched.hip", "adjoint.hip", "trsv.hip"],
+    "libcqr.so": ["cqr.hip", "gemm_f64.hip", "chol_f64.hip", "gemm_bf16.hip", "mixed.hip", "batched.hip", "adjoint.hip", "trsv.hip", "tall.hip"],
     "libcqr_synth.so": ["synth.hip"],
 }
 

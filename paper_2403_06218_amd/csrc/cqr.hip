@@ -167,11 +167,40 @@ __global__ void set_status_kernel(int* status, int v0, int v1) {
 // (q x w, ldq), gated on the status word.  Writes the projections into the
 // segments' H and the triangular factor into Rjj (w x w, ldr).
 int orth_block(int64_t q, int64_t w, double* Q, int64_t ldq, const Seg* seg, int nseg, double* Rjj, int64_t ldr,
-               const Work& ws, int blk, hipStream_t st) {
+               const Work& ws, int blk, hipStream_t st, bool allow_tall = true) {
   const int* gate = ws.status;
   const double dq = (double)q, dw = (double)w;
   int64_t stot = 0;
   for (int i = 0; i < nseg; ++i) stot += seg[i].s;
+  if (allow_tall && nseg <= 1 && tall_eligible(q, w, stot)) {
+    // Narrow block of a tall matrix: the same steps as below, fused into
+    // row-streaming sweeps (S1; S2+S3; S4; S5+S6; S7+S8; S9; S10).
+    const int s = (int)stot, wi = (int)w;
+    const double* P = nseg ? seg[0].P : nullptr;
+    const int64_t ldp = nseg ? seg[0].ldp : 1;
+    double* H = nseg ? seg[0].H : nullptr;
+    const int64_t ldh = nseg ? seg[0].ldh : 1;
+    // The block Q is read until the last step writes it: the first pass
+    // leaves its update in T (T = Q - P H, then T L^{-T} in place).
+    if (s > 0) CQR_TRY(tall_proj(q, s, wi, P, ldp, Q, ldq, H, ldh, ws.part, ws.part_cap, gate, st));
+    CQR_TRY(tall_update_gram(q, s, wi, P, ldp, H, ldh, Q, ldq, ws.T, q, ws.W, ws.part, ws.part_cap, gate, st));
+    CQR_TRY(chol_inv(wi, ws.W, w, ws.LT1, ws.XT1, ws.status, 1, blk, st));
+    const double* X1 = s > 0 ? ws.T : Q;
+    const int64_t ldx1 = s > 0 ? q : ldq;
+    CQR_TRY(tall_trsm_proj(q, s, wi, X1, ldx1, ws.XT1, ws.T, q, P, ldp, ws.Hb, s > 0 ? s : 1, ws.part, ws.part_cap,
+                           gate, st));
+    CQR_TRY(tall_update_gram(q, s, wi, P, ldp, ws.Hb, s > 0 ? s : 1, ws.T, q, ws.T, q, ws.W, ws.part, ws.part_cap,
+                             gate, st));
+    CQR_TRY(chol_inv(wi, ws.W, w, ws.LT2, ws.XT2, ws.status, 2, blk, st));
+    CQR_TRY(tall_trsm_proj(q, 0, wi, ws.T, q, ws.XT2, Q, ldq, nullptr, 1, nullptr, 1, ws.part, ws.part_cap, gate,
+                           st));
+    CQR_TRY(gemm_nn(ROLE_SMALL, w, w, w, 1.0, ws.LT2, w, ws.LT1, w, 0.0, Rjj, ldr, gate, st,
+                    dw * dw * dw));  // S11 R = Lb^T L^T
+    if (s > 0)
+      CQR_TRY(gemm_nn(ROLE_SMALL, s, w, w, 1.0, ws.Hb, s, ws.LT1, w, 1.0, H, ldh, gate, st,
+                      dw * (double)s));  // S12 H = H + Hb L^T
+    return CQR_OK;
+  }
   const double gram_flops = (nseg > 0 ? 2.0 : 1.0) * dw * dw * dq;  // Table 1: b^2 q (Alg. 4), 2 b^2 q (Alg. 5)
   // ---- pass 1
   for (int i = 0; i < nseg; ++i)  // S1  H = P^T Q
@@ -228,15 +257,15 @@ int reset_status(const Work& ws, hipStream_t st) {
 }
 
 // Fallback for the block of columns [c0, c0 + w) of Q: restore the input from
-// ws.save and orthogonalise column by column (Algorithm 5 with b = 1) against
+// ws.save (when `restore`; the row-streaming form leaves it intact) and orthogonalise column by column (Algorithm 5 with b = 1) against
 // `pre` (up to one segment of earlier basis vectors) and the block's earlier
 // columns.  Hcol(c) gives where column c's projection on `pre` goes.
 // Returns CQR status; sets *zero if a column had no component left.
 int fallback_block(int64_t q, int64_t w, double* Qblk, int64_t ldq, const Seg* pre, double* Hpre, int64_t ldhpre,
-                   double* Rblk, int64_t ldr, const Work& ws, int blk, hipStream_t st, bool* zero) {
+                   double* Rblk, int64_t ldr, const Work& ws, int blk, hipStream_t st, bool* zero, bool restore) {
   int rc = reset_status(ws, st);
   if (rc) return rc;
-  CQR_TRY(copy_matrix(q, w, ws.save, q, Qblk, ldq, nullptr, st));
+  if (restore) CQR_TRY(copy_matrix(q, w, ws.save, q, Qblk, ldq, nullptr, st));
   if (pre && pre->s > 0) CQR_TRY(zero_matrix(pre->s, w, Hpre, ldhpre, st));
   CQR_TRY(zero_matrix(w, w, Rblk, ldr, st));
   *zero = false;
@@ -245,7 +274,7 @@ int fallback_block(int64_t q, int64_t w, double* Qblk, int64_t ldq, const Seg* p
     int nseg = 0;
     if (pre && pre->s > 0) segs[nseg++] = Seg{pre->P, pre->ldp, pre->s, Hpre + c * ldhpre, ldhpre};
     if (c > 0) segs[nseg++] = Seg{Qblk, ldq, c, Rblk + c * ldr, ldr};
-    rc = orth_block(q, 1, Qblk + c * ldq, ldq, segs, nseg, Rblk + c + c * ldr, ldr, ws, blk, st);
+    rc = orth_block(q, 1, Qblk + c * ldq, ldq, segs, nseg, Rblk + c + c * ldr, ldr, ws, blk, st, false);
     if (rc) return rc;
     int stv[2];
     rc = read_status(ws, st, stv);
@@ -321,7 +350,9 @@ int cqr_factor(int64_t q, int64_t r, int64_t b, double* Y, int64_t ldy, double* 
       const int64_t s = blk * b;
       const int64_t w = (r - s < b) ? (r - s) : b;
       double* Qj = Y + s * ldy;
-      CQR_TRY(copy_matrix(q, w, Qj, ldy, ws.save, q, ws.status, st));
+      // The row-streaming form leaves the block intact on a breakdown; the
+      // GEMM form works in place and keeps a copy for the fallback.
+      if (!tall_eligible(q, w, s)) CQR_TRY(copy_matrix(q, w, Qj, ldy, ws.save, q, ws.status, st));
       Seg seg{Y, ldy, s, R + s * ldr, ldr};
       rc = orth_block(q, w, Qj, ldy, &seg, s > 0 ? 1 : 0, R + s + s * ldr, ldr, ws, (int)blk, st);
       if (rc) return rc;
@@ -336,7 +367,7 @@ int cqr_factor(int64_t q, int64_t r, int64_t b, double* Y, int64_t ldy, double* 
     Seg pre{Y, ldy, s, nullptr, 0};
     bool zero = false;
     rc = fallback_block(q, w, Y + s * ldy, ldy, &pre, R + s * ldr, ldr, R + s + s * ldr, ldr, ws, (int)blk, st,
-                        &zero);
+                        &zero, !tall_eligible(q, w, s));
     if (rc) return rc;
     if (block_flags) block_flags[blk] |= CQR_FLAG_FALLBACK | (zero ? CQR_FLAG_ZERO_COL : 0);
     if (info && *info == 0) *info = (int32_t)(blk + 1);
@@ -389,7 +420,7 @@ int cqr_orth_against(int64_t q, int64_t b, int64_t s, double* Q, int64_t ldq, co
   if (rc) return rc;
   if (stv[0] != 0) {
     bool zero = false;
-    rc = fallback_block(q, b, Q, ldq, &seg, H, ldh, R, ldr, ws, 0, st, &zero);
+    rc = fallback_block(q, b, Q, ldq, &seg, H, ldh, R, ldr, ws, 0, st, &zero, true);
     if (rc) return rc;
     if (info) *info = 1;
   }

@@ -77,6 +77,26 @@ hipError_t chol_inv(int b, const double* W, int64_t ldw, double* LT, double* XT,
 hipError_t chol_inv_wide(int b, double* W, int64_t ldw, double* LT, double* XT, double* tmp, int* status, int code,
                          int blk, hipStream_t s);
 
+// Row-streaming steps of CGS-CQR2 for a narrow block (w <= 16 columns, s <= 128
+// basis columns, q >= 16384 rows): tall_eligible tells whether they apply.
+// The block is written only by the last step, so a breakdown leaves it intact.
+// tall_proj:        H (s x w, ldh) = P^T X.
+// tall_update_gram: Y = X - P H (no update when s == 0; Y may be X), then
+//                   W (w x w, ld w) = Y^T Y.
+// tall_trsm_proj:   T = X XT (XT w x w, ld w); if s > 0 and Hb != NULL also
+//                   Hb (s x w, ldhb) = P^T T.
+// Partial sums go through `part` (capacity part_cap doubles); every kernel is
+// gated on *gate == 0.
+bool tall_eligible(int64_t q, int64_t w, int64_t s);
+hipError_t tall_proj(int64_t q, int s, int w, const double* P, int64_t ldp, const double* X, int64_t ldx, double* H,
+                     int64_t ldh, double* part, size_t part_cap, const int* gate, hipStream_t st);
+hipError_t tall_update_gram(int64_t q, int s, int w, const double* P, int64_t ldp, const double* H, int64_t ldh,
+                            const double* X, int64_t ldx, double* Y, int64_t ldy, double* W, double* part,
+                            size_t part_cap, const int* gate, hipStream_t st);
+hipError_t tall_trsm_proj(int64_t q, int s, int w, const double* X, int64_t ldx, const double* XT, double* T,
+                          int64_t ldt, const double* P, int64_t ldp, double* Hb, int64_t ldhb, double* part,
+                          size_t part_cap, const int* gate, hipStream_t st);
+
 // dst (rows x cols, ldd) = src (rows x cols, lds); gated on *gate == 0 when gate != NULL.
 hipError_t copy_matrix(int64_t rows, int64_t cols, const double* src, int64_t lds, double* dst, int64_t ldd,
                        const int* gate, hipStream_t s);
