@@ -13,13 +13,13 @@
 // P (q x s, the finished basis) has s <= 128 columns.  A workgroup (8 waves)
 // owns a contiguous range of rows and walks it in 16-row tiles, one tile per
 // wave at a time, with FP64 MFMA (16x16x4): the 16 rows of a tile are the
-// reduction dimension of the P^T products and the M dimension of the
-// products with small right factors.  In the 16x16x4 layout, lane l holds
-// C(l/16 + 4v, l%16) in element v, and for the k-step v the same lane
-// supplies A(l%16, l/16) and B(l/16, l%16); hence element v of a 16 x 16
-// result tile is exactly the A or B operand of k-step v when the result's
-// rows are used as the reduction dimension of the next product (X^T X, P^T T)
-// without leaving registers.
+// reduction dimension of the P^T products and the N dimension of the
+// (transposed) products with small right factors.  In the 16x16x4 layout
+// lane l supplies A(l%16, l/16) and B(l/16, l%16) and holds C(l/16 + 4v,
+// l%16) in element v; every global load and store is arranged so that a
+// lane touches one row (16 consecutive rows per instruction), and a tile is
+// moved to the rows-as-reduction form through LDS only where a product
+// reduces over rows.
 //
 // The reductions over rows end in per-workgroup partial sums, combined by
 // tall_reduce_kernel in a fixed order (results do not depend on timing).
@@ -61,6 +61,18 @@ __device__ __forceinline__ void tall_store_partial(const td4 (&acc)[MT], double*
   }
 }
 
+// Global accesses use the coalesced form "row li, column lg + 4 v" (16
+// consecutive rows of 4 columns per instruction).  tr16 turns a wave's
+// 16 x 16 tile held that way into the form "row 4 v + lg, column li" (the
+// reduction-over-rows operand of the 16x16x4 MFMA) through the wave's own
+// LDS scratch; LDS operations of one wave complete in order, so no barrier.
+__device__ __forceinline__ void tr16(const double (&in)[4], double (&out)[4], double* tb, int li, int lg) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) tb[li * 17 + lg + 4 * v] = in[v];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) out[v] = tb[(4 * v + lg) * 17 + li];
+}
+
 // S1: partial H = P[rows]^T X[rows] (s x w).
 template <int MT>
 __global__ void __launch_bounds__(kTallThreads)
@@ -68,34 +80,42 @@ tall_proj_kernel(int64_t q, int s, int w, const double* __restrict__ P, int64_t 
                  int64_t ldx, int64_t ch, double* __restrict__ part, const int* __restrict__ gate) {
   if (gate != nullptr && *gate != 0) return;
   __shared__ double sred[kTallWaves * 256];
+  __shared__ double stb[kTallWaves * 16 * 17];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
+  double* tb = stb + wave * 16 * 17;
   const int64_t r0 = (int64_t)blockIdx.x * ch, r1 = (r0 + ch < q) ? r0 + ch : q;
   td4 acc[MT];
 #pragma unroll
   for (int t = 0; t < MT; ++t) acc[t] = td4{0.0, 0.0, 0.0, 0.0};
   for (int64_t row0 = r0 + 16 * wave; row0 < r1; row0 += 16 * kTallWaves) {
-    double xv[4], pv[MT][4];
+    const int64_t row = row0 + li;
+    const bool rok = row < r1;
+    double xl[4], pl[MT][4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int64_t row = row0 + 4 * v + lg;
-      xv[v] = (row < r1 && li < w) ? X[row + li * ldx] : 0.0;
+      const int c = lg + 4 * v;
+      xl[v] = (rok && c < w) ? X[row + c * ldx] : 0.0;
 #pragma unroll
-      for (int t = 0; t < MT; ++t) {
-        const int c = 16 * t + li;
-        pv[t][v] = (row < r1 && c < s) ? P[row + c * ldp] : 0.0;
-      }
+      for (int t = 0; t < MT; ++t) pl[t][v] = (rok && 16 * t + c < s) ? P[row + (16 * t + c) * ldp] : 0.0;
     }
+    double xv[4];
+    tr16(xl, xv, tb, li, lg);
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
+    for (int t = 0; t < MT; ++t) {
+      double pv[4];
+      tr16(pl[t], pv, tb, li, lg);
 #pragma unroll
-      for (int t = 0; t < MT; ++t) acc[t] = tmma(pv[t][v], xv[v], acc[t]);
+      for (int v = 0; v < 4; ++v) acc[t] = tmma(pv[v], xv[v], acc[t]);
+    }
   }
   tall_store_partial<MT>(acc, sred, part, blockIdx.x, lane, wave, tid);
 }
 
 // S2 + S3 (S7 + S8): Y[rows] = X[rows] - P[rows] H (skipped when s == 0; Y may
-// be X), then the partial W = Y[rows]^T Y[rows] (w x w).
+// be X), then the partial W = Y[rows]^T Y[rows] (w x w).  The update is
+// formed transposed, (P H)^T = H^T P^T, so that its result is held row per
+// lane like the coalesced loads and stores.
 template <int MT>
 __global__ void __launch_bounds__(kTallThreads)
 tall_update_gram_kernel(int64_t q, int s, int w, const double* __restrict__ P, int64_t ldp,
@@ -103,112 +123,127 @@ tall_update_gram_kernel(int64_t q, int s, int w, const double* __restrict__ P, i
                         int64_t ldy, int64_t ch, double* __restrict__ part, const int* __restrict__ gate) {
   if (gate != nullptr && *gate != 0) return;
   __shared__ double sred[kTallWaves * 256];
+  __shared__ double stb[kTallWaves * 16 * 17];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
+  double* tb = stb + wave * 16 * 17;
   const int64_t r0 = (int64_t)blockIdx.x * ch, r1 = (r0 + ch < q) ? r0 + ch : q;
-  // B operand of the update, k-step (t, v): H(16 t + 4 v + lg, li).
-  double hb[MT][4];
+  // A operand of H^T P^T, k-step (t, v): H(16 t + 4 v + lg, li).
+  double ha[MT][4];
 #pragma unroll
   for (int t = 0; t < MT; ++t)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int k = 16 * t + 4 * v + lg;
-      hb[t][v] = (k < s && li < w) ? H[k + li * ldh] : 0.0;
+      ha[t][v] = (k < s && li < w) ? H[k + li * ldh] : 0.0;
     }
   td4 g[1] = {td4{0.0, 0.0, 0.0, 0.0}};
   for (int64_t row0 = r0 + 16 * wave; row0 < r1; row0 += 16 * kTallWaves) {
-    // Rows of the result tile: row0 + lg + 4 v (element v of this lane).
+    const int64_t row = row0 + li;
+    const bool rok = row < r1;
+    // Element v: row `row`, column lg + 4 v.
     double x[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int64_t row = row0 + lg + 4 * v;
-      x[v] = (row < r1 && li < w) ? X[row + li * ldx] : 0.0;
+      const int c = lg + 4 * v;
+      x[v] = (rok && c < w) ? X[row + c * ldx] : 0.0;
     }
     if (s > 0) {
-      // A operand, k-step (t, v): P(row0 + li, 16 t + 4 v + lg).
-      double pa[MT][4];
-      const int64_t arow = row0 + li;
+      // B operand, k-step (t, v): P(row, 16 t + 4 v + lg).
+      double pb[MT][4];
 #pragma unroll
       for (int t = 0; t < MT; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int c = 16 * t + 4 * v + lg;
-          pa[t][v] = (arow < r1 && c < s) ? P[arow + c * ldp] : 0.0;
+          pb[t][v] = (rok && c < s) ? P[row + c * ldp] : 0.0;
         }
       td4 c = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int t = 0; t < MT; ++t)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) c = tmma(pa[t][v], hb[t][v], c);
+        for (int v = 0; v < 4; ++v) c = tmma(ha[t][v], pb[t][v], c);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t row = row0 + lg + 4 * v;
+        const int col = lg + 4 * v;
         x[v] -= c[v];
-        if (row < r1 && li < w) Y[row + li * ldy] = x[v];
+        if (rok && col < w) Y[row + col * ldy] = x[v];
       }
     }
+    double xt[4];
+    tr16(x, xt, tb, li, lg);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) g[0] = tmma(x[v], x[v], g[0]);
+    for (int v = 0; v < 4; ++v) g[0] = tmma(xt[v], xt[v], g[0]);
   }
   tall_store_partial<1>(g, sred, part, blockIdx.x, lane, wave, tid);
 }
 
-// S5 (S10): T[rows] = X[rows] XT (XT = (L^{-1})^T, w x w); with PROJ also the
-// partial Hb = P[rows]^T T[rows] of the next pass (S6).
+// S5 (S10): T[rows] = X[rows] XT (XT = (L^{-1})^T, w x w), formed transposed
+// (XT^T X^T) so that T is held row per lane; with PROJ also the partial
+// Hb = P[rows]^T T[rows] of the next pass (S6).  X and T may be the same
+// array (each tile is read before it is written, by the same wave).
 template <int MT, bool PROJ>
 __global__ void __launch_bounds__(kTallThreads)
-tall_trsm_proj_kernel(int64_t q, int s, int w, const double* __restrict__ X, int64_t ldx,
-                      const double* __restrict__ XT, double* __restrict__ T, int64_t ldt,
-                      const double* __restrict__ P, int64_t ldp, int64_t ch, double* __restrict__ part,
-                      const int* __restrict__ gate) {
+tall_trsm_proj_kernel(int64_t q, int s, int w, const double* X, int64_t ldx, const double* __restrict__ XT,
+                      double* T, int64_t ldt, const double* __restrict__ P, int64_t ldp, int64_t ch,
+                      double* __restrict__ part, const int* __restrict__ gate) {
   if (gate != nullptr && *gate != 0) return;
   __shared__ double sred[kTallWaves * 256];
+  __shared__ double stb[kTallWaves * 16 * 17];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
+  double* tb = stb + wave * 16 * 17;
   const int64_t r0 = (int64_t)blockIdx.x * ch, r1 = (r0 + ch < q) ? r0 + ch : q;
-  // B operand, k-step v: XT(4 v + lg, li).
-  double xb[4];
+  // A operand of XT^T X^T, k-step v: XT(4 v + lg, li).
+  double xa[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int k = 4 * v + lg;
-    xb[v] = (k < w && li < w) ? XT[k + li * w] : 0.0;
+    xa[v] = (k < w && li < w) ? XT[k + li * w] : 0.0;
   }
   td4 acc[MT];
 #pragma unroll
   for (int t = 0; t < MT; ++t) acc[t] = td4{0.0, 0.0, 0.0, 0.0};
   for (int64_t row0 = r0 + 16 * wave; row0 < r1; row0 += 16 * kTallWaves) {
-    const int64_t arow = row0 + li;
-    double xa[4];
+    const int64_t row = row0 + li;
+    const bool rok = row < r1;
+    // B operand, k-step v: X(row, 4 v + lg).
+    double xb[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int c = 4 * v + lg;
-      xa[v] = (arow < r1 && c < w) ? X[arow + c * ldx] : 0.0;
+      xb[v] = (rok && c < w) ? X[row + c * ldx] : 0.0;
     }
-    double pv[MT][4];
+    double pl[MT][4];
     if constexpr (PROJ) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t row = row0 + 4 * v + lg;
+        const int c = lg + 4 * v;
 #pragma unroll
-        for (int t = 0; t < MT; ++t) {
-          const int c = 16 * t + li;
-          pv[t][v] = (row < r1 && c < s) ? P[row + c * ldp] : 0.0;
-        }
+        for (int t = 0; t < MT; ++t) pl[t][v] = (rok && 16 * t + c < s) ? P[row + (16 * t + c) * ldp] : 0.0;
       }
     }
     td4 c = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int v = 0; v < 4; ++v) c = tmma(xa[v], xb[v], c);
+    // Element v of c: T(row, lg + 4 v).
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int64_t row = row0 + lg + 4 * v;
-      if (row < r1 && li < w) T[row + li * ldt] = c[v];
+      const int col = lg + 4 * v;
+      if (rok && col < w) T[row + col * ldt] = c[v];
     }
     if constexpr (PROJ) {
+      double cv[4], tt[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
+      for (int v = 0; v < 4; ++v) cv[v] = c[v];
+      tr16(cv, tt, tb, li, lg);
 #pragma unroll
-        for (int t = 0; t < MT; ++t) acc[t] = tmma(pv[t][v], c[v], acc[t]);
+      for (int t = 0; t < MT; ++t) {
+        double pv[4];
+        tr16(pl[t], pv, tb, li, lg);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[t] = tmma(pv[v], tt[v], acc[t]);
+      }
     }
   }
   if constexpr (PROJ) tall_store_partial<MT>(acc, sred, part, blockIdx.x, lane, wave, tid);
@@ -250,7 +285,7 @@ tall_reduce_kernel(int M, int N, int Mp, int G, const double* __restrict__ part,
   }
 }
 
-int tall_mt(int s) { return s <= 16 ? 1 : s <= 32 ? 2 : s <= 64 ? 4 : 8; }
+int tall_mt(int s) { return s <= 16 ? 1 : s <= 32 ? 2 : s <= 48 ? 3 : s <= 64 ? 4 : 8; }
 
 int64_t tall_rows_per_group(int64_t q) {
   const int64_t tiles = (q + 15) / 16;
@@ -286,6 +321,7 @@ hipError_t tall_proj(int64_t q, int s, int w, const double* P, int64_t ldp, cons
   switch (MT) {
     case 1: hipLaunchKernelGGL(tall_proj_kernel<1>, grid, block, 0, st, q, s, w, P, ldp, X, ldx, ch, part, gate); break;
     case 2: hipLaunchKernelGGL(tall_proj_kernel<2>, grid, block, 0, st, q, s, w, P, ldp, X, ldx, ch, part, gate); break;
+    case 3: hipLaunchKernelGGL(tall_proj_kernel<3>, grid, block, 0, st, q, s, w, P, ldp, X, ldx, ch, part, gate); break;
     case 4: hipLaunchKernelGGL(tall_proj_kernel<4>, grid, block, 0, st, q, s, w, P, ldp, X, ldx, ch, part, gate); break;
     default: hipLaunchKernelGGL(tall_proj_kernel<8>, grid, block, 0, st, q, s, w, P, ldp, X, ldx, ch, part, gate); break;
   }
@@ -307,6 +343,7 @@ hipError_t tall_update_gram(int64_t q, int s, int w, const double* P, int64_t ld
   switch (MT) {
     case 1: hipLaunchKernelGGL(tall_update_gram_kernel<1>, grid, block, 0, st, q, s, w, P, ldp, H, ldh, X, ldx, Y, ldy, ch, part, gate); break;
     case 2: hipLaunchKernelGGL(tall_update_gram_kernel<2>, grid, block, 0, st, q, s, w, P, ldp, H, ldh, X, ldx, Y, ldy, ch, part, gate); break;
+    case 3: hipLaunchKernelGGL(tall_update_gram_kernel<3>, grid, block, 0, st, q, s, w, P, ldp, H, ldh, X, ldx, Y, ldy, ch, part, gate); break;
     case 4: hipLaunchKernelGGL(tall_update_gram_kernel<4>, grid, block, 0, st, q, s, w, P, ldp, H, ldh, X, ldx, Y, ldy, ch, part, gate); break;
     default: hipLaunchKernelGGL(tall_update_gram_kernel<8>, grid, block, 0, st, q, s, w, P, ldp, H, ldh, X, ldx, Y, ldy, ch, part, gate); break;
   }
@@ -334,6 +371,7 @@ hipError_t tall_trsm_proj(int64_t q, int s, int w, const double* X, int64_t ldx,
     switch (MT) {
       case 1: hipLaunchKernelGGL((tall_trsm_proj_kernel<1, true>), grid, block, 0, st, q, s, w, X, ldx, XT, T, ldt, P, ldp, ch, part, gate); break;
       case 2: hipLaunchKernelGGL((tall_trsm_proj_kernel<2, true>), grid, block, 0, st, q, s, w, X, ldx, XT, T, ldt, P, ldp, ch, part, gate); break;
+      case 3: hipLaunchKernelGGL((tall_trsm_proj_kernel<3, true>), grid, block, 0, st, q, s, w, X, ldx, XT, T, ldt, P, ldp, ch, part, gate); break;
       case 4: hipLaunchKernelGGL((tall_trsm_proj_kernel<4, true>), grid, block, 0, st, q, s, w, X, ldx, XT, T, ldt, P, ldp, ch, part, gate); break;
       default: hipLaunchKernelGGL((tall_trsm_proj_kernel<8, true>), grid, block, 0, st, q, s, w, X, ldx, XT, T, ldt, P, ldp, ch, part, gate); break;
     }
