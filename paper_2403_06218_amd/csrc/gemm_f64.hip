@@ -68,6 +68,10 @@ gemm_reg_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __r
                 const double* __restrict__ B, int64_t ldb, double beta, double* C, int64_t ldc, int64_t kchunk,
                 double* __restrict__ part, const int* __restrict__ gate) {
   if (gate != nullptr && *gate != 0) return;
+  if constexpr (TA && ROLE == ROLE_GRAM && MT == NT) {
+    // W = Q^T Q is symmetric; its strictly lower tiles are not formed.
+    if (M == N && blockIdx.x > blockIdx.y) return;
+  }
   constexpr int WM = 2, WN = 2;
   constexpr int WTM = MT / WM, WTN = NT / WN;
   constexpr int SM = WTM / 16, SN = WTN / 16;
@@ -85,7 +89,11 @@ gemm_reg_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __r
   const int64_t m0 = (int64_t)blockIdx.x * MT;
   const int64_t n0 = (int64_t)blockIdx.y * NT;
   const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
-  const int64_t kend = (K < kbeg + kchunk) ? K : kbeg + kchunk;
+  int64_t kend = (K < kbeg + kchunk) ? K : kbeg + kchunk;
+  if constexpr (!TA && (ROLE == ROLE_TRSM || ROLE == ROLE_SMALL)) {
+    // B is upper triangular: rows k >= n0 + NT of this tile's columns are zero.
+    if (n0 + NT < kend) kend = n0 + NT;
+  }
   const int nst = (kend > kbeg) ? (int)((kend - kbeg + KT - 1) / KT) : 0;
 
   // Global->register staging.  Every thread loads APT elements of A and BPT of
@@ -237,6 +245,10 @@ gemm_dma_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __r
                 double* __restrict__ part, const int* __restrict__ gate) {
   static_assert(S == 2 || S == 3, "ring depth");
   if (gate != nullptr && *gate != 0) return;
+  if constexpr (TA && ROLE == ROLE_GRAM && MT == NT) {
+    // W = Q^T Q is symmetric; its strictly lower tiles are not formed.
+    if (M == N && blockIdx.x > blockIdx.y) return;
+  }
   constexpr int KT = kDmaKT;
   constexpr int NW = WM * WN;
   constexpr int WTM = MT / WM, WTN = NT / WN;
@@ -267,7 +279,12 @@ gemm_dma_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __r
   const int64_t m0 = (int64_t)blockIdx.x * MT;
   const int64_t n0 = (int64_t)blockIdx.y * NT;
   const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
-  const int64_t kend = (K < kbeg + kchunk) ? K : kbeg + kchunk;
+  int64_t kend = (K < kbeg + kchunk) ? K : kbeg + kchunk;
+  if constexpr (!TA && (ROLE == ROLE_TRSM || ROLE == ROLE_SMALL)) {
+    // B is upper triangular: rows k >= n0 + NT of this tile's columns are zero
+    // (n0 + NT is a multiple of the stage depth).
+    if (n0 + NT < kend) kend = n0 + NT;
+  }
   const int nst = (kend > kbeg) ? (int)((kend - kbeg) / KT) : 0;
 
   // Source offsets (elements from the stage origin) of this lane's chunks.
@@ -467,7 +484,7 @@ void pick_tile(bool ta, int64_t M, int64_t N, int nsplit, int* mt, int* nt) {
 }
 
 Plan plan_gemm(bool ta, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B, int64_t ldb,
-               bool allow_split, size_t part_cap) {
+               bool allow_split, size_t part_cap, bool sym = false) {
   Plan p;
   p.dma = dma_eligible(ta, M, K, A, lda, B, ldb);
   const int kt = p.dma ? kDmaKT : kKT;
@@ -506,7 +523,12 @@ Plan plan_gemm(bool ta, int64_t M, int64_t N, int64_t K, const double* A, int64_
     // 512 resident slots (two per CU) as closely as possible, each split
     // walking at least 8 stages and fitting the partial-sum buffer; among
     // equally full choices the fewest splits win (less reduction traffic).
-    const int64_t tiles = tiles_for(M, N, M > 64 ? 128 : 64, N > 64 ? 128 : 64);
+    int64_t tiles = tiles_for(M, N, M > 64 ? 128 : 64, N > 64 ? 128 : 64);
+    if (sym) {
+      // Only the tiles on or above the diagonal are formed (symmetric Gram).
+      const int64_t tm = (M + 127) / 128;
+      if (M > 64) tiles = tm * (tm + 1) / 2;
+    }
     int64_t max_split = K / (8 * kt);
     const int64_t by_cap = (int64_t)(part_cap / (size_t)(M * N));
     if (max_split > by_cap) max_split = by_cap;
@@ -599,7 +621,7 @@ hipError_t gemm_tn(Role role, int64_t M, int64_t N, int64_t K, double alpha, con
                    const int* gate, hipStream_t s, double flops) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (!ld_ok(lda) || !ld_ok(ldb)) return hipErrorInvalidValue;
-  const Plan p = plan_gemm(true, M, N, K, A, lda, B, ldb, part != nullptr, part_cap);
+  const Plan p = plan_gemm(true, M, N, K, A, lda, B, ldb, part != nullptr, part_cap, role == ROLE_GRAM && M == N);
   const double bytes = 8.0 * ((double)K * M + (double)K * N + (double)M * N * (beta != 0.0 ? 2.0 : 1.0));
   double* pp = p.nsplit > 1 ? part : nullptr;
   const int slot = prof_begin(s);

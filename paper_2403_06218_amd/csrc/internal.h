@@ -13,9 +13,10 @@ namespace cqr {
 enum Role : int {
   ROLE_PROJ = 0,    // H = P^T Q        (Alg. 5 S1/S6)          TN GEMM, split-K
   ROLE_UPDATE,      // Q = Q - P H      (Alg. 5 S2/S7)          NN GEMM
-  ROLE_GRAM,        // W = Q^T Q        (Alg. 4 S1/S4, 5 S3/S8) TN GEMM, split-K
-  ROLE_TRSM,        // Q = Q L^{-T}     (Alg. 4 S3/S6, 5 S5/S10) NN GEMM by (L^{-1})^T
-  ROLE_SMALL,       // R = Lb^T L^T, H += Hbar L^T (Alg. 5 S11/S12)
+  ROLE_GRAM,        // W = Q^T Q        (Alg. 4 S1/S4, 5 S3/S8) TN GEMM, split-K; for M == N the
+                    //                  strictly lower tiles (tile height) of W are left unwritten
+  ROLE_TRSM,        // Q = Q L^{-T}     (Alg. 4 S3/S6, 5 S5/S10) NN GEMM by (L^{-1})^T; B upper triangular
+  ROLE_SMALL,       // R = Lb^T L^T, H += Hbar L^T (Alg. 5 S11/S12); B upper triangular
   ROLE_REDUCE,      // split-K partial sums -> C
   ROLE_CHOL,        // W = L L^T and L^{-1}  (Alg. 4 S2/S5, 5 S4/S9)
   ROLE_COPY,        // block save / restore for the breakdown fallback
