@@ -131,3 +131,38 @@ def test_fp8_ir_solve_reaches_fp64_residual(n, b):
     xo, rc = oracle.qr_solve(ref["Q"], ref["R"], rhs)
     assert rc == 0
     assert np.abs(xh - xo).max() < 16 * np.linalg.cond(Y) * n * EPS * np.abs(xo).max()
+
+
+@pytest.mark.parametrize("prec", [cqr.PREC_BF16, cqr.PREC_FP8])
+def test_large_factor_and_refinement_properties(prec):
+    """n = 16384, b = 256: the later projections have at least 12288 rows of
+    output and take the 256-row tile.  Properties that hold at any size (the
+    oracle would take minutes): reconstruction and orthogonality within the
+    precision's bounds, an exact upper triangle with a positive diagonal, and
+    the refined solution under the FP64 HPL bar (residual recomputed here)."""
+    n, b = 16384, 256
+    u = U_BF16 if prec == cqr.PREC_BF16 else U_FP8
+    Y = cqr.colmajor(n, n)
+    cqr.synth_uniform(Y, 77, -0.5, 0.5)
+    Y.diagonal().zero_()
+    Y.diagonal().copy_(Y.abs().sum(dim=1) + 1.0)
+    rhs = torch.empty(n, dtype=torch.float64, device="cuda")
+    cqr.synth_uniform(rhs.view(n, 1), 78)
+    Q, R, info = cqr.qr_mixed(Y, b, prec=prec)
+    torch.cuda.synchronize()
+    assert info == 0
+    assert not torch.tril(R, -1).any()
+    assert (R.diagonal() > 0).all()
+    Qd, Rd = Q.double(), R.double()
+    rec = float(torch.linalg.norm(Y - Qd @ Rd) / torch.linalg.norm(Y))
+    assert rec < 2 * u, rec
+    G = Qd.t().contiguous() @ Qd
+    G.diagonal().sub_(1.0)
+    orth = float(G.abs().max())
+    assert orth < 4 * u, orth
+    del Qd, Rd, G
+    x, iters, res = cqr.solve_ir(Y, Q, R, rhs, maxiter=50, tol=16.0)
+    assert res < 16 and iters <= 10, (res, iters)
+    r = (Y @ x - rhs).abs().max()
+    hpl = float(r / (Y.abs().sum(dim=1).max() * x.abs().max() * n * EPS))
+    assert hpl < 16, hpl
