@@ -281,21 +281,25 @@ unsigned grid_of(int64_t total) {
 
 // ---------------------------------------------------------------- refinement
 
-// part[c][i] = sum over columns j in chunk c of |Y(i, j)| (absval) or Y(i, j) x_j.
+// part[c][i] = sum over columns j in chunk c of Y(i, j) x_j; with ABS also
+// pabs[c][i] = the same sum of |Y(i, j)| (the row sums of ||Y||_inf, taken
+// in the same pass over Y).
 template <bool ABS>
 __global__ void __launch_bounds__(256)
 gemv_n_part_kernel(int64_t n, const double* __restrict__ Y, int64_t ldy, const double* __restrict__ x, int64_t chunk,
-                   double* __restrict__ part) {
+                   double* __restrict__ part, double* __restrict__ pabs) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t c = blockIdx.y;
   if (i >= n) return;
   const int64_t j0 = c * chunk, j1 = (j0 + chunk < n) ? j0 + chunk : n;
-  double acc = 0.0;
+  double acc = 0.0, aab = 0.0;
   for (int64_t j = j0; j < j1; ++j) {
     const double y = Y[i + j * ldy];
-    acc += ABS ? fabs(y) : y * x[j];
+    acc += y * x[j];
+    if (ABS) aab += fabs(y);
   }
   part[c * n + i] = acc;
+  if (ABS) pabs[c * n + i] = aab;
 }
 
 // r = rhs - sum_c part[c] (or the row sums themselves when rhs == nullptr);
@@ -334,7 +338,10 @@ __global__ void __launch_bounds__(256) max_kernel(int64_t n, const double* __res
   if (threadIdx.x == 0) *out = red[0];
 }
 
-// y = Q^T v with FP32 Q, FP64 v and accumulation: one wave per column.
+// y = Q^T v with FP32 Q, FP64 v and accumulation: one wave per column; with
+// VEC (16-byte aligned columns) each lane reads 4 consecutive entries at a
+// time into four accumulators, added in a fixed order at the end.
+template <bool VEC>
 __global__ void __launch_bounds__(256)
 gemv_t_f32_kernel(int64_t n, const float* __restrict__ Q, int64_t ldq, const double* __restrict__ v,
                   double* __restrict__ y) {
@@ -343,7 +350,21 @@ gemv_t_f32_kernel(int64_t n, const float* __restrict__ Q, int64_t ldq, const dou
   if (j >= n) return;
   const float* qc = Q + j * ldq;
   double acc = 0.0;
-  for (int64_t i = lane; i < n; i += 64) acc += (double)qc[i] * v[i];
+  if constexpr (VEC) {
+    double a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int64_t i = 4 * lane;
+    for (; i + 3 < n; i += 256) {
+      const float4 q4 = *(const float4*)(qc + i);
+      acc += (double)q4.x * v[i];
+      a1 += (double)q4.y * v[i + 1];
+      a2 += (double)q4.z * v[i + 2];
+      a3 += (double)q4.w * v[i + 3];
+    }
+    for (int64_t t = i; t < n && t < i + 4; ++t) acc += (double)qc[t] * v[t];
+    acc = (acc + a1) + (a2 + a3);
+  } else {
+    for (int64_t i = lane; i < n; i += 64) acc += (double)qc[i] * v[i];
+  }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
   if (lane == 0) y[j] = acc;
@@ -527,7 +548,7 @@ int cqr_solve_ir_workspace_size(int64_t n, size_t* bytes) {
   if (n < 0) return -1;
   if (!bytes) return -2;
   const int64_t nchunk = 16;
-  *bytes = a256((size_t)(nchunk + 4) * (size_t)(n > 0 ? n : 1) * 8) + a256((size_t)((n + 255) / 256 + 8) * 8) +
+  *bytes = a256((size_t)(2 * nchunk + 4) * (size_t)(n > 0 ? n : 1) * 8) + a256((size_t)((n + 255) / 256 + 8) * 8) +
            trsv_workspace_bytes(n);
   return CQR_OK;
 }
@@ -556,37 +577,46 @@ int cqr_solve_ir(int64_t n, const double* Y, int64_t ldy, const float* Q, int64_
   const int nchunk = 16;
   const int64_t chunk = (n + nchunk - 1) / nchunk;
   double* part = (double*)work;                 // nchunk x n
-  double* r = part + (int64_t)nchunk * n;       // residual
+  double* pabs = part + (int64_t)nchunk * n;    // nchunk x n (row sums of |Y|)
+  double* r = pabs + (int64_t)nchunk * n;       // residual
   double* c = r + n;                            // Q^T r, then d
-  double* bm = (double*)((char*)work + a256((size_t)(nchunk + 4) * n * 8));  // block maxima, then scalars
+  double* bm = (double*)((char*)work + a256((size_t)(2 * nchunk + 4) * n * 8));  // block maxima, then scalars
   const int64_t nblk = (n + 255) / 256;
   double* scal = bm + nblk;                     // [0] |Y|_inf [1] |r|_inf [2] |x|_inf
-  void* tw = (char*)work + a256((size_t)(nchunk + 4) * n * 8) + a256((size_t)(nblk + 8) * 8);
+  void* tw = (char*)work + a256((size_t)(2 * nchunk + 4) * n * 8) + a256((size_t)(nblk + 8) * 8);
+  const bool vec = (ldq % 4 == 0) && !(reinterpret_cast<uintptr_t>(Q) & 15);
   const unsigned* terr = trsv_error_word(n, tw);
   MX_TRY(trsv_prepare(n, true, R, ldr, tw, st));
   const dim3 gpart((unsigned)nblk, (unsigned)nchunk);
-  // ||Y||_inf once.
-  hipLaunchKernelGGL(gemv_n_part_kernel<true>, gpart, dim3(256), 0, st, n, Y, ldy, (const double*)nullptr, chunk, part);
-  MX_TRY(hipGetLastError());
-  hipLaunchKernelGGL(residual_kernel, dim3((unsigned)nblk), dim3(256), 0, st, n, nchunk, part, (const double*)nullptr,
-                     (double*)nullptr, bm);
-  MX_TRY(hipGetLastError());
-  hipLaunchKernelGGL(max_kernel, dim3(1), dim3(256), 0, st, nblk, bm, scal + 0);
-  MX_TRY(hipGetLastError());
   // x = 0, r = rhs.
   MX_TRY(zero_matrix(n, 1, x, n, st));
   MX_TRY(copy_matrix(n, 1, rhs, n, r, n, nullptr, st));
   const double eps = 2.220446049250313e-16;
   for (int it = 1; it <= maxiter; ++it) {
     // d = R^{-1} Q^T r
-    hipLaunchKernelGGL(gemv_t_f32_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, n, Q, ldq, r, c);
+    if (vec)
+      hipLaunchKernelGGL(gemv_t_f32_kernel<true>, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, n, Q, ldq, r, c);
+    else
+      hipLaunchKernelGGL(gemv_t_f32_kernel<false>, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, n, Q, ldq, r, c);
     MX_TRY(hipGetLastError());
     MX_TRY(trsv_solve(n, true, R, ldr, tw, c, it - 1, st));
     hipLaunchKernelGGL(axpy_kernel, dim3((unsigned)nblk), dim3(256), 0, st, n, c, x);
     MX_TRY(hipGetLastError());
-    // r = rhs - Y x, ||r||_inf, ||x||_inf
-    hipLaunchKernelGGL(gemv_n_part_kernel<false>, gpart, dim3(256), 0, st, n, Y, ldy, x, chunk, part);
-    MX_TRY(hipGetLastError());
+    // r = rhs - Y x, ||r||_inf, ||x||_inf; in the first step also ||Y||_inf
+    // from the same pass over Y.
+    if (it == 1) {
+      hipLaunchKernelGGL(gemv_n_part_kernel<true>, gpart, dim3(256), 0, st, n, Y, ldy, x, chunk, part, pabs);
+      MX_TRY(hipGetLastError());
+      hipLaunchKernelGGL(residual_kernel, dim3((unsigned)nblk), dim3(256), 0, st, n, nchunk, pabs,
+                         (const double*)nullptr, (double*)nullptr, bm);
+      MX_TRY(hipGetLastError());
+      hipLaunchKernelGGL(max_kernel, dim3(1), dim3(256), 0, st, nblk, bm, scal + 0);
+      MX_TRY(hipGetLastError());
+    } else {
+      hipLaunchKernelGGL(gemv_n_part_kernel<false>, gpart, dim3(256), 0, st, n, Y, ldy, x, chunk, part,
+                         (double*)nullptr);
+      MX_TRY(hipGetLastError());
+    }
     hipLaunchKernelGGL(residual_kernel, dim3((unsigned)nblk), dim3(256), 0, st, n, nchunk, part, rhs, r, bm);
     MX_TRY(hipGetLastError());
     hipLaunchKernelGGL(max_kernel, dim3(1), dim3(256), 0, st, nblk, bm, scal + 1);
