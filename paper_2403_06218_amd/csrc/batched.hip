@@ -139,7 +139,7 @@ __device__ void trsm_rows(T* sQ, const T* sL, const T* sDinv, int n, int tid, in
 }
 
 template <typename T, int NMAX, int BW, int NW>
-__global__ __launch_bounds__(NW * 64) void batch_kernel(BatchArgs ar) {
+__global__ __launch_bounds__(NW * 64, (NW == 4 && NMAX <= 128) ? 2 : 1) void batch_kernel(BatchArgs ar) {
   static_assert(BW == 16 || BW == 32, "block width");
   constexpr int NT = NW * 64;
   constexpr int LDW = BW + 1;
@@ -570,6 +570,14 @@ const Instance kInstances[] = {
     {CQR_F32, 256, 32, 8, batch_kernel<float, 256, 32, 8>},
     {CQR_F32, 512, 16, 4, batch_kernel<float, 512, 16, 4>},
     {CQR_F32, 512, 32, 8, batch_kernel<float, 512, 32, 8>},
+    // Small-size instances: less LDS and fewer registers, so that several
+    // matrices share a CU and hide each other's latency.
+    {CQR_F64, 64, 16, 4, batch_kernel<double, 64, 16, 4>},
+    {CQR_F64, 128, 16, 4, batch_kernel<double, 128, 16, 4>},
+    {CQR_F64, 128, 16, 8, batch_kernel<double, 128, 16, 8>},
+    {CQR_F32, 64, 16, 4, batch_kernel<float, 64, 16, 4>},
+    {CQR_F32, 128, 16, 4, batch_kernel<float, 128, 16, 4>},
+    {CQR_F32, 128, 16, 8, batch_kernel<float, 128, 16, 8>},
 };
 constexpr int kNumInstances = (int)(sizeof(kInstances) / sizeof(kInstances[0]));
 
