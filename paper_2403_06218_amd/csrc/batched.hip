@@ -138,8 +138,8 @@ __device__ void trsm_rows(T* sQ, const T* sL, const T* sDinv, int n, int tid, in
   }
 }
 
-template <typename T, int NMAX, int BW, int NW>
-__global__ __launch_bounds__(NW * 64, (NW == 4 && NMAX <= 128) ? 2 : 1) void batch_kernel(BatchArgs ar) {
+template <typename T, int NMAX, int BW, int NW, int OCC = (NW == 4 && NMAX <= 128) ? 2 : 1>
+__global__ __launch_bounds__(NW * 64, OCC) void batch_kernel(BatchArgs ar) {
   static_assert(BW == 16 || BW == 32, "block width");
   constexpr int NT = NW * 64;
   constexpr int LDW = BW + 1;
@@ -578,6 +578,7 @@ const Instance kInstances[] = {
     {CQR_F32, 64, 16, 4, batch_kernel<float, 64, 16, 4>},
     {CQR_F32, 128, 16, 4, batch_kernel<float, 128, 16, 4>},
     {CQR_F32, 128, 16, 8, batch_kernel<float, 128, 16, 8>},
+    {CQR_F32, 256, 16, 4, batch_kernel<float, 256, 16, 4, 2>},  // two per CU
 };
 constexpr int kNumInstances = (int)(sizeof(kInstances) / sizeof(kInstances[0]));
 
