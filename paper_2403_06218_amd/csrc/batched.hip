@@ -138,7 +138,7 @@ __device__ void trsm_rows(T* sQ, const T* sL, const T* sDinv, int n, int tid, in
   }
 }
 
-template <typename T, int NMAX, int BW, int NW, int OCC = (NW == 4 && NMAX <= 128) ? 2 : 1>
+template <typename T, int NMAX, int BW, int NW, int OCC = (NW == 4 && NMAX <= 128) ? 2 : 1, int PBF = 0>
 __global__ __launch_bounds__(NW * 64, OCC) void batch_kernel(BatchArgs ar) {
   static_assert(BW == 16 || BW == 32, "block width");
   constexpr int NT = NW * 64;
@@ -147,19 +147,23 @@ __global__ __launch_bounds__(NW * 64, OCC) void batch_kernel(BatchArgs ar) {
   constexpr int MAXCT = BW / 16;
   constexpr int RSZ = (NW * 256 > NMAX ? NW * 256 : NMAX);
   // Two chunk buffers when they fit beside the block, else one.
-  constexpr int PB = ((2 * NMAX * 16 + NMAX * BW) * (int)sizeof(T) <= 100 * 1024) ? 2 : 1;
+  constexpr int PB = PBF ? PBF : (((2 * NMAX * 16 + NMAX * BW) * (int)sizeof(T) <= 100 * 1024) ? 2 : 1);
   constexpr int TPC = NT / 16;                   // loader threads per chunk column
   constexpr int PRE = (NMAX + TPC - 1) / TPC;    // chunk elements per loader thread
   using V = typename Mf<T>::V;
 
   __shared__ T sQ[NMAX * BW];
   __shared__ T sP[PB][NMAX * 16];  // 16 finished columns of P (swizzled, ld 16)
-  __shared__ T sH[16 * BW];        // projection of one chunk
+  // The projection of one chunk (chunk loop) and the Gram (after it) share storage.
+  __shared__ T sHW[(16 * BW > BW * LDW) ? 16 * BW : BW * LDW];
+  T* const sH = sHW;
+  T* const sW = sHW;
   __shared__ T sR2[RSZ];           // projection / Gram partial tiles; fallback projections
-  __shared__ T sW[BW * LDW];
   __shared__ T sL[2][BW * LDW];
   __shared__ T sDinv[2][BW];
-  __shared__ T sY[NMAX];
+  // y = Q^T b waits in the subdiagonal of R (R(c + 1, c) holds y_c; the last
+  // entry here) until the back substitution, which restores the zeros.
+  __shared__ T sYlast;
   __shared__ T sRed[NW];
   __shared__ int sInt[2];
 
@@ -183,10 +187,6 @@ __global__ __launch_bounds__(NW * 64, OCC) void batch_kernel(BatchArgs ar) {
     const int bw = ar.bw;
     const int nblk = (n + bw - 1) / bw;
     int info = 0, flags = 0;
-
-    for (int r = tid; r < np; r += NT) {
-      sY[r] = T(0);
-    }
 
     for (int j = 0; j < nblk; ++j) {
       const int s = j * bw;
@@ -369,6 +369,7 @@ __global__ __launch_bounds__(NW * 64, OCC) void batch_kernel(BatchArgs ar) {
         const int rows = n - s;
         for (int e = tid; e < rows * w; e += NT) {
           const int rr = e % rows, c = e / rows;
+          if (rr == c + 1) continue;  // y_{s+c} goes there
           T v = T(0);
           if (rr <= c)
             for (int p = rr; p <= c; ++p) v += sL[1][p * LDW + rr] * sL[0][c * LDW + p];
@@ -379,7 +380,10 @@ __global__ __launch_bounds__(NW * 64, OCC) void batch_kernel(BatchArgs ar) {
           if (Bv)
             for (int r = lane; r < n; r += 64) d += sQ[sw(r, c, BW)] * Bv[r];
           d = wave_sum(d);
-          if (lane == 0) sY[s + c] = d;
+          if (lane == 0) {
+            if (s + c + 1 < n) R[(size_t)(s + c + 1) + (size_t)(s + c) * ldr] = d;
+            else sYlast = d;
+          }
         }
         for (int e = tid; e < n * w; e += NT) {
           const int r = e % n, c = e / n;
@@ -439,7 +443,7 @@ __global__ __launch_bounds__(NW * 64, OCC) void batch_kernel(BatchArgs ar) {
           if (fail) flags |= CQR_FLAG_ZERO_COL;
           for (int r = tid; r < n; r += NT) {
             A[(size_t)r + (size_t)col * lda] = fail ? T(0) : sV[r];
-            if (r > col) R[(size_t)r + (size_t)col * ldr] = T(0);
+            if (r > col + 1) R[(size_t)r + (size_t)col * ldr] = T(0);
           }
           if (tid == 0) R[(size_t)col + (size_t)col * ldr] = fail ? T(0) : lp1 * lp0;
           if (wave == 0) {
@@ -447,15 +451,30 @@ __global__ __launch_bounds__(NW * 64, OCC) void batch_kernel(BatchArgs ar) {
             if (!fail)
               for (int r = lane; r < n; r += 64) d += sV[r] * (Bv ? Bv[r] : T(0));
             d = wave_sum(d);
-            if (lane == 0) sY[col] = d;
+            if (lane == 0) {
+              if (col + 1 < n) R[(size_t)(col + 1) + (size_t)col * ldr] = d;
+              else sYlast = d;
+            }
           }
           __syncthreads();
         }
       }
     }
 
-    // Back substitution R x = y, block by block from the last.
+    // Back substitution R x = y, block by block from the last, with y gathered
+    // from the subdiagonal of R into the (now free) block buffer.
     if (Bv) {
+      T* const sY = sQ;
+      __syncthreads();
+      for (int r = tid; r < n; r += NT) {
+        if (r + 1 < n) {
+          sY[r] = R[(size_t)(r + 1) + (size_t)r * ldr];
+          R[(size_t)(r + 1) + (size_t)r * ldr] = T(0);
+        } else {
+          sY[r] = sYlast;
+        }
+      }
+      __syncthreads();
       for (int J = nblk - 1; J >= 0; --J) {
         const int s = J * bw, w = min(bw, n - s);
         if (wave == 0) {
@@ -579,6 +598,7 @@ const Instance kInstances[] = {
     {CQR_F32, 128, 16, 4, batch_kernel<float, 128, 16, 4>},
     {CQR_F32, 128, 16, 8, batch_kernel<float, 128, 16, 8>},
     {CQR_F32, 256, 16, 4, batch_kernel<float, 256, 16, 4, 2>},  // two per CU
+    {CQR_F64, 256, 16, 4, batch_kernel<double, 256, 16, 4, 2, 1>},  // two per CU: single chunk buffer
 };
 constexpr int kNumInstances = (int)(sizeof(kInstances) / sizeof(kInstances[0]));
 
