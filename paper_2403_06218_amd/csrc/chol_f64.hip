@@ -1,6 +1,6 @@
 // Small dense kernels: the b x b Cholesky factorisation with the inverse of
 // its factor (Table 1 POTRF, run on the GPU instead of the host), block
-// copies, and the two kernels of the triangular solve.
+// copies, and the matrix-vector product Q^T b of the solve.
 #include "internal.h"
 #include "wave_chol.h"
 
@@ -233,12 +233,53 @@ unsigned grid_for(int64_t total) {
 
 }  // namespace
 
+// The same contract for b <= 16 in one wave, registers only: lane i < 16
+// holds row i of W, factors it with wave_chol, forms row i of X = L^{-1}
+// as in the diagonal blocks above, and writes column i of LT and of XT.
+__global__ void __launch_bounds__(64)
+chol_inv16_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __restrict__ LT, double* __restrict__ XT,
+                  int64_t ldo, int* status, int code, int blk) {
+  if (status[0] != 0) return;
+  const int lane = threadIdx.x;
+  double a[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j)
+    a[j] = (lane < b && j <= lane) ? W[lane + (int64_t)j * ldw] : ((lane == j) ? 1.0 : 0.0);
+  double lii, linv;
+  const bool ok = wave_chol<double, 16>(a, lii, linv, lane);
+  double xr[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) xr[j] = (j == lane) ? 1.0 : 0.0;
+#pragma unroll
+  for (int k = 0; k < 15; ++k) {
+    const double mik = (lane > k) ? a[k] * linv : 0.0;
+#pragma unroll
+    for (int j = 0; j <= k; ++j) xr[j] -= mik * wave_bcast(xr[j], k);
+  }
+  // LT(j, i) = L(i, j) and XT(j, i) = X(i, j) = (M^{-1})_ij / L_jj.
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const double djinv = wave_bcast(linv, j);
+    if (lane < b && j < b) {
+      LT[j + (int64_t)lane * ldo] = (j < lane) ? a[j] : ((j == lane) ? lii : 0.0);
+      XT[j + (int64_t)lane * ldo] = (j < lane) ? xr[j] * djinv : ((j == lane) ? linv : 0.0);
+    }
+  }
+  if (lane == 0 && !ok) {
+    status[1] = blk;
+    status[0] = code;
+  }
+}
+
 static hipError_t chol_inv_ld(int b, const double* W, int64_t ldw, double* LT, double* XT, int64_t ldo, int* status,
                        int code, int blk, hipStream_t s) {
   if (b < 1 || b > kCB) return hipErrorInvalidValue;
   const double bb = (double)b;
   const int slot = prof_begin(s);
-  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(256), 0, s, b, W, ldw, LT, XT, ldo, status, code, blk);
+  if (b <= 16)
+    hipLaunchKernelGGL(chol_inv16_kernel, dim3(1), dim3(64), 0, s, b, W, ldw, LT, XT, ldo, status, code, blk);
+  else
+    hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(256), 0, s, b, W, ldw, LT, XT, ldo, status, code, blk);
   hipError_t e = hipGetLastError();
   prof_end(slot, ROLE_CHOL, s, bb * bb * bb / 3.0, 8.0 * 3.0 * bb * bb);
   return e;
