@@ -1,11 +1,13 @@
 // Adjoint of the solve x = A^{-1} b with A = Q R (stored factors of the
 // batched form): for an upstream gradient g = dL/dx,
 //   lambda = A^{-T} g = Q (R^{-T} g),   dL/dA = -lambda x^T,   dL/db = lambda.
-// One workgroup per matrix: the triangular solve R^T z = g is blocked by 32
-// (a dot product per column against the finished part of z, then the 32 x 32
-// triangle in one wave with readlane), lambda = Q z one row per thread, and the
-// rank-1 product written column by column (coalesced).  HBM-bound on reading
-// Q and R and writing dA.
+// One 1024-thread workgroup per matrix: the triangular solve R^T z = g is
+// blocked by 32 (a dot product per column against the finished part of z, one
+// wave per column, then the 32 x 32 triangle in one wave with readlane),
+// lambda = Q z with two threads per row (each half of the columns, four
+// accumulators, then added in a fixed order), and the rank-1 product written
+// column by column (coalesced), the columns split between the two halves.
+// HBM-bound on reading Q and R and writing dA.
 #include "internal.h"
 #include "../../include/cqr.h"
 
@@ -33,7 +35,7 @@ __device__ __forceinline__ T wsum(T x) {
 }
 
 constexpr int kAdjNMax = 512;
-constexpr int kAdjThreads = 512;
+constexpr int kAdjThreads = 1024;
 
 struct AdjArgs {
   const int32_t* n;
@@ -54,6 +56,7 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(AdjArgs a) {
   __shared__ T sz[kAdjNMax];  // g, then z = R^{-T} g
   __shared__ T sx[kAdjNMax];
   __shared__ T sl[kAdjNMax];  // lambda
+  __shared__ T sh[kAdjNMax];  // second half of each row's sum
   const int m = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n = a.n[m];
@@ -103,19 +106,39 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(AdjArgs a) {
     }
     __syncthreads();
   }
-  // lambda = Q z; db = lambda.
-  for (int r = tid; r < n; r += kAdjThreads) {
-    T d = T(0);
-    for (int c = 0; c < n; ++c) d += Q[(size_t)r + (size_t)c * ldq] * sz[c];
-    sl[r] = d;
-    db[r] = d;
+  // lambda = Q z; db = lambda.  Thread (r, h) sums columns [h n/2, (h+1) n/2).
+  {
+    const int r = tid % kAdjNMax, h = tid / kAdjNMax;
+    const int c0 = h ? n / 2 : 0, c1 = h ? n : n / 2;
+    if (r < n) {
+      const T* qr = Q + r;
+      T d0 = T(0), d1 = T(0), d2 = T(0), d3 = T(0);
+      int c = c0;
+      for (; c + 3 < c1; c += 4) {
+        d0 += qr[(size_t)c * ldq] * sz[c];
+        d1 += qr[(size_t)(c + 1) * ldq] * sz[c + 1];
+        d2 += qr[(size_t)(c + 2) * ldq] * sz[c + 2];
+        d3 += qr[(size_t)(c + 3) * ldq] * sz[c + 3];
+      }
+      for (; c < c1; ++c) d0 += qr[(size_t)c * ldq] * sz[c];
+      const T d = (d0 + d1) + (d2 + d3);
+      if (h) sh[r] = d; else sl[r] = d;
+    }
+    __syncthreads();
+    if (h == 0 && r < n) {
+      const T lam = sl[r] + sh[r];
+      sl[r] = lam;
+      db[r] = lam;
+    }
   }
   __syncthreads();
-  // dA = -lambda x^T.
-  for (int c = 0; c < n; ++c) {
-    const T xc = sx[c];
-    T* col = dA + (size_t)c * ldda;
-    for (int r = tid; r < n; r += kAdjThreads) col[r] = -sl[r] * xc;
+  // dA = -lambda x^T: thread (r, h) writes row r of the columns c = h mod 2.
+  {
+    const int r = tid % kAdjNMax, h = tid / kAdjNMax;
+    if (r < n) {
+      const T lr = -sl[r];
+      for (int c = h; c < n; c += 2) dA[(size_t)r + (size_t)c * ldda] = lr * sx[c];
+    }
   }
 }
 
