@@ -27,6 +27,8 @@ METRIC = "GFLOP/s at n=32768: BF16-MFMA LU+FP64 IR vs FP64 LUPP, HPL resid<16"
 PEAK_FP64_MFMA_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
+PEAK_BF16_MFMA_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak
+PEAK_FP8_MFMA_TFLOPS = 5000.0  # MI355X dense FP8 matrix peak
 
 
 def parse():
@@ -124,7 +126,15 @@ def bench_mixed(cqr, torch, n: int, b: int, K: int, W: int, seed: int, fp64_ms: 
             roles[name] = {"ms": round(r["ms"], 3), "launches": r["launches"],
                            "tflops": round(r["flops"] / (r["ms"] * 1e-3) / 1e12, 2) if r["flops"] else None}
     flops = costmodel.ca3(b, n, n) + costmodel.solve_flops(n)
+    # Matrix-core roofline of the dominant low-precision kernel role (projection
+    # or update), from the library's launch timing of the factorisation above.
+    lp = {k: v for k, v in roles.items() if k in ("proj", "update") and v["tflops"]}
+    dom = max(lp, key=lambda k: lp[k]["ms"]) if lp else None
+    peak = PEAK_BF16_MFMA_TFLOPS if prec == 1 else PEAK_FP8_MFMA_TFLOPS
+    roofline = ({"bound": "mfma", "kernel": dom, "achieved": lp[dom]["tflops"], "peak": peak, "unit": "TFLOP/s",
+                 "frac": round(lp[dom]["tflops"] / peak, 4)} if dom else None)
     return {"value": round(flops / el / 1e9, 2), "unit": "GFLOP/s", "ms_per_step": round(el * 1e3, 2),
+            "roofline": roofline,
             "factor_ms": round(tf * 1e3, 2), "speedup_vs_fp64": round(fp64_ms / (el * 1e3), 3) if fp64_ms else None,
             "ir_iterations": [o[1] for o in out], "hpl_scaled_residual": [o[2] for o in out],
             "info": [o[0] for o in out], "dtype": ("bf16" if prec == 1 else "fp8 e4m3 (per-column pow2 scales)") + " mfma (fp32 acc) + f64 panel + f64 refinement",
