@@ -101,17 +101,23 @@ size_t mixed_layout(int64_t q, int64_t r, int64_t b, int prec, char* base, Mixed
 }
 
 // dst (bf16, rows_pad x cols, ld ldd) = bf16(src (rows x cols, lds)); rows
-// rows..rows_pad-1 are zero.
+// rows..rows_pad-1 are zero.  Column j = blockIdx.y; each thread converts 4
+// consecutive rows and stores them as one 8-byte word (rows_pad and ldd are
+// multiples of 4, dst 8-byte aligned).
+constexpr int kCvtRows = 4 * 256;  // rows per workgroup of the conversion kernels
 __global__ void __launch_bounds__(256)
 to_bf16_kernel(int64_t rows, int64_t rows_pad, int64_t cols, const double* __restrict__ src, int64_t lds,
                __bf16* __restrict__ dst, int64_t ldd, const int* __restrict__ gate) {
   if (gate != nullptr && *gate != 0) return;
-  const int64_t total = rows_pad * cols;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = idx % rows_pad, j = idx / rows_pad;
-    dst[i + j * ldd] = (i < rows) ? (__bf16)src[i + j * lds] : (__bf16)0.0f;
-  }
+  const int64_t j = blockIdx.y;
+  const int64_t i0 = (int64_t)blockIdx.x * kCvtRows + 4 * threadIdx.x;
+  if (j >= cols || i0 >= rows_pad) return;
+  const double* sc = src + j * lds;
+  typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+  bf4 o;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) o[u] = (i0 + u < rows) ? (__bf16)sc[i0 + u] : (__bf16)0.0f;
+  *(bf4*)(dst + i0 + j * ldd) = o;
 }
 
 // ---------------------------------------------------------------- FP8 operands
@@ -135,28 +141,30 @@ __device__ __forceinline__ float pow2_scale(double m) {
 }
 
 // cmax[j] = max_i |src(i, j) * rowscale[i]| (rowscale may be NULL); one
-// workgroup per column, 8 loads in flight per thread.  Maxima are exact, so
-// the order of the reduction does not matter.
-__global__ void __launch_bounds__(256)
+// 1024-thread workgroup per column, 8 loads in flight per thread.  Maxima are
+// exact, so the order of the reduction does not matter.
+constexpr int kColmaxThreads = 1024;
+__global__ void __launch_bounds__(kColmaxThreads)
 colmax_kernel(int64_t rows, const double* __restrict__ src, int64_t lds, const float* __restrict__ rowscale,
               double* __restrict__ cmax, const int* __restrict__ gate) {
   if (gate != nullptr && *gate != 0) return;
-  __shared__ double red[256];
+  constexpr int T = kColmaxThreads;
+  __shared__ double red[T];
   const int j = blockIdx.x, t = threadIdx.x;
   const double* col = src + (int64_t)j * lds;
   double m = 0.0;
   int64_t i0 = t;
-  for (; i0 + 7 * 256 < rows; i0 += 8 * 256) {
+  for (; i0 + 7 * T < rows; i0 += 8 * T) {
     double v[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = col[i0 + u * 256] * (rowscale ? (double)rowscale[i0 + u * 256] : 1.0);
+    for (int u = 0; u < 8; ++u) v[u] = col[i0 + u * T] * (rowscale ? (double)rowscale[i0 + u * T] : 1.0);
 #pragma unroll
     for (int u = 0; u < 8; ++u) m = fmax(m, fabs(v[u]));
   }
-  for (; i0 < rows; i0 += 256) m = fmax(m, fabs(col[i0] * (rowscale ? (double)rowscale[i0] : 1.0)));
+  for (; i0 < rows; i0 += T) m = fmax(m, fabs(col[i0] * (rowscale ? (double)rowscale[i0] : 1.0)));
   red[t] = m;
   __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
+  for (int h = T / 2; h > 0; h >>= 1) {
     if (t < h) red[t] = red[t + h] > red[t] ? red[t + h] : red[t];
     __syncthreads();
   }
@@ -165,21 +173,28 @@ colmax_kernel(int64_t rows, const double* __restrict__ src, int64_t lds, const f
 
 // dst (FP8, rows_pad x cols, ld ldd) = e4m3(src(i, j) * rowscale[i] * s_j)
 // with s_j from cmax[j]; colinv[j] = 1 / s_j; rows >= rows are zero.
+// Column j = blockIdx.y; each thread converts 4 consecutive rows and stores
+// them as one 4-byte word (rows_pad and ldd are multiples of 4).
 __global__ void __launch_bounds__(256)
 to_fp8_kernel(int64_t rows, int64_t rows_pad, int64_t cols, const double* __restrict__ src, int64_t lds,
               const float* __restrict__ rowscale, const double* __restrict__ cmax, uint8_t* __restrict__ dst,
               int64_t ldd, float* __restrict__ colinv, const int* __restrict__ gate) {
   if (gate != nullptr && *gate != 0) return;
-  const int64_t total = rows_pad * cols;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = idx % rows_pad, j = idx / rows_pad;
-    const float sc = pow2_scale(cmax[j]);
-    uint8_t v = 0;
-    if (i < rows) v = to_e4m3((float)(src[i + j * lds] * (rowscale ? (double)rowscale[i] : 1.0) * (double)sc));
-    dst[i + j * ldd] = v;
-    if (i == 0) colinv[j] = 1.f / sc;
+  const int64_t j = blockIdx.y;
+  const int64_t i0 = (int64_t)blockIdx.x * kCvtRows + 4 * threadIdx.x;
+  if (j >= cols || i0 >= rows_pad) return;
+  const float sc = pow2_scale(cmax[j]);
+  const double* scol = src + j * lds;
+  uint32_t word = 0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t i = i0 + u;
+    uint32_t v = 0;
+    if (i < rows) v = to_e4m3((float)(scol[i] * (rowscale ? (double)rowscale[i] : 1.0) * (double)sc));
+    word |= v << (8 * u);
   }
+  *(uint32_t*)(dst + i0 + j * ldd) = word;
+  if (i0 == 0) colinv[j] = 1.f / sc;
 }
 
 // A finished block Qj (q x w, FP64): Q32[:, c0:c0+w] = float(Qj),
@@ -270,6 +285,11 @@ __global__ void __launch_bounds__(256) zero_f32_kernel(int64_t rows, int64_t col
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x)
     X[idx % rows + (idx / rows) * ldx] = 0.f;
+}
+
+// Grid of the conversion kernels: kCvtRows rows by one column per workgroup.
+dim3 cvt_grid(int64_t rows_pad, int64_t cols) {
+  return dim3((unsigned)((rows_pad + kCvtRows - 1) / kCvtRows), (unsigned)cols);
 }
 
 unsigned grid_of(int64_t total) {
@@ -388,13 +408,13 @@ int mixed_block(int64_t q, int64_t w, int64_t s, const double* Yj, int64_t ldy, 
     double* X = pass == 0 ? ws.Qj : ws.T;      // block being orthogonalised
     double* Hx = pass == 0 ? ws.H : ws.Hb;     // its projection (s x w, ld rp)
     if (s > 0) {
-      hipLaunchKernelGGL(to_bf16_kernel, dim3(grid_of(ws.qp * w)), dim3(256), 0, st, q, ws.qp, w, X, q, ws.B16, ws.qp,
+      hipLaunchKernelGGL(to_bf16_kernel, cvt_grid(ws.qp, w), dim3(256), 0, st, q, ws.qp, w, X, q, ws.B16, ws.qp,
                          gate);
       MX_TRY(hipGetLastError());
       // S1/S6: H = P^T X  (BF16 x BF16 -> FP32, reduced into FP64)
       MX_TRY(gemm_bf16_tn(ROLE_PROJ, s, w, ws.qp, 1.0f, ws.P16, ws.qp, ws.B16, ws.qp, 0.0f, Hx, ws.rp, true, ws.part,
                           ws.part_cap, gate, st, 2.0 * dw * dq * ds));
-      hipLaunchKernelGGL(to_bf16_kernel, dim3(grid_of(sp * w)), dim3(256), 0, st, s, sp, w, Hx, ws.rp, ws.H16, ws.rp,
+      hipLaunchKernelGGL(to_bf16_kernel, cvt_grid(sp, w), dim3(256), 0, st, s, sp, w, Hx, ws.rp, ws.H16, ws.rp,
                          gate);
       MX_TRY(hipGetLastError());
       // S2/S7: X -= P H  (A = P^T stored k-contiguous, K = s padded with zeros)
@@ -439,19 +459,19 @@ int mixed_block_fp8(int64_t q, int64_t w, int64_t s, const double* Yj, int64_t l
     double* X = pass == 0 ? ws.Qj : ws.T;
     double* Hx = pass == 0 ? ws.H : ws.Hb;
     if (s > 0) {
-      hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)w), dim3(256), 0, st, q, X, q, (const float*)nullptr, ws.cmax,
+      hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)w), dim3(kColmaxThreads), 0, st, q, X, q, (const float*)nullptr, ws.cmax,
                          gate);
       MX_TRY(hipGetLastError());
-      hipLaunchKernelGGL(to_fp8_kernel, dim3(grid_of(ws.qp * w)), dim3(256), 0, st, q, ws.qp, w, X, q,
+      hipLaunchKernelGGL(to_fp8_kernel, cvt_grid(ws.qp, w), dim3(256), 0, st, q, ws.qp, w, X, q,
                          (const float*)nullptr, ws.cmax, ws.B8, ws.qp, ws.binv, gate);
       MX_TRY(hipGetLastError());
       // S1/S6: H = P^T X, undone scales: rows by 1/s_P, columns by 1/s_X.
       MX_TRY(gemm_fp8_tn(ROLE_PROJ, s, w, ws.qp, 1.0f, ws.P8, ws.qp, ws.B8, ws.qp, 0.0f, Hx, ws.rp, true, ws.pinv,
                          ws.binv, ws.part, ws.part_cap, gate, st, 2.0 * dw * dq * ds));
       // H' = diag(1/s_P) H, then per-column scales for its FP8 copy.
-      hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)w), dim3(256), 0, st, s, Hx, ws.rp, ws.pinv, ws.cmax, gate);
+      hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)w), dim3(kColmaxThreads), 0, st, s, Hx, ws.rp, ws.pinv, ws.cmax, gate);
       MX_TRY(hipGetLastError());
-      hipLaunchKernelGGL(to_fp8_kernel, dim3(grid_of(sp * w)), dim3(256), 0, st, s, sp, w, Hx, ws.rp, ws.pinv,
+      hipLaunchKernelGGL(to_fp8_kernel, cvt_grid(sp, w), dim3(256), 0, st, s, sp, w, Hx, ws.rp, ws.pinv,
                          ws.cmax, ws.H8, ws.rp, ws.hinv, gate);
       MX_TRY(hipGetLastError());
       // S2/S7: X -= (P diag(s_P)) (diag(1/s_P) H), columns undone by 1/s_H.
@@ -475,7 +495,7 @@ int mixed_block_fp8(int64_t q, int64_t w, int64_t s, const double* Yj, int64_t l
   hipLaunchKernelGGL(to_f32_kernel, dim3(grid_of(w * w)), dim3(256), 0, st, w, w, ws.Rjj, w, R32 + s + s * ldr, ldr,
                      gate);
   MX_TRY(hipGetLastError());
-  hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)w), dim3(256), 0, st, q, ws.Qj, q, (const float*)nullptr, ws.cmax,
+  hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)w), dim3(kColmaxThreads), 0, st, q, ws.Qj, q, (const float*)nullptr, ws.cmax,
                      gate);
   MX_TRY(hipGetLastError());
   hipLaunchKernelGGL(finish_block_fp8_kernel, dim3((unsigned)((q + 63) / 64), (unsigned)((w + 63) / 64)), dim3(256),
