@@ -30,13 +30,13 @@ constexpr int kCLD = kCB + 1;  // LDS row stride (odd: column walks are conflict
 //      X = L^{-1}:  X_i,0:i = -X_ii (L_i,0:i X_0:i,0:i) (MFMA), one tile per
 //      wave, so that the serial diagonal work hides the rest;
 //   2. the rows below take L = A X_pp^T (MFMA).
-// The last block row of X follows the loop.  A pivot that is not > 0 (NaN
+// The last block row of X follows the loop.  Finished parts of LT and XT go
+// out during the loop, written by waves 1-3 while wave 0 is busy.  A pivot that is not > 0 (NaN
 // included) marks a breakdown; the kernel runs to the end and reports it in
 // status.
 __global__ void __launch_bounds__(256)
 chol_inv_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __restrict__ LT, double* __restrict__ XT,
                 int64_t ldo, int* status, int code, int blk) {
-  if (status[0] != 0) return;
   __shared__ double sA[kCB * kCLD];
   __shared__ double sD[kCB];
   __shared__ double sT[16 * kCLD];
@@ -55,6 +55,8 @@ chol_inv_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __rest
       const int j = rj + 2 * u;
       v[u] = (ri < b && j < b) ? W[ri + (int64_t)j * ldw] : (ri == j ? 1.0 : 0.0);
     }
+    // W is always readable: its loads are issued before the status test.
+    if (status[0] != 0) return;
 #pragma unroll
     for (int u = 0; u < kCB / 2; ++u) {
       const int j = rj + 2 * u;
@@ -106,6 +108,24 @@ chol_inv_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __rest
     for (int v = 0; v < 4; ++v) sA[(16 * jt + li) * kCLD + r0 + lg + 4 * v] = -x[v];
   };
 
+  // Output rows LT(j, :) for the 16-row panel jp (L's column panel jp, final
+  // once that panel's rows below are formed) and output columns XT(:, i)
+  // for X's block row ip (final once its off-diagonal tiles are formed), by
+  // threads t0 .. t0 + nt - 1.  Column i of LT holds L(i, 0:i), column i of
+  // XT holds X(i, 0:i); the rest is zero.
+  auto store_lt_panel = [&](int jp, int t0, int nt) {
+    for (int e = tid - t0; e < 16 * b; e += nt) {
+      const int j = 16 * jp + (e & 15), i = e >> 4;
+      if (j < b) LT[j + (int64_t)i * ldo] = (i >= j) ? sA[i * kCLD + j] : 0.0;
+    }
+  };
+  auto store_xt_row = [&](int ip, int t0, int nt) {
+    for (int e = tid - t0; e < 16 * kCB; e += nt) {
+      const int j = e & (kCB - 1), i = 16 * ip + (e >> 7);
+      if (i < b && j < b) XT[j + (int64_t)i * ldo] = (i > j) ? sA[j * kCLD + i] : ((i == j) ? sD[i] : 0.0);
+    }
+  };
+
   for (int p = 0; p < P; ++p) {
     const int c0 = 16 * p;
     if (wave == 0) {
@@ -149,6 +169,10 @@ chol_inv_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __rest
         for (int t = p + wave; t < P; t += 3) panel_update(t, c0);
       if (p >= 2)
         for (int jt = wave - 1; jt < p - 1; jt += 3) inverse_tile(p - 1, jt);
+      // Waves 1-3 have slack while wave 0 factors the diagonal block: they
+      // write out L's panel p-1 and X's block row p-2, both final.
+      if (p >= 1) store_lt_panel(p - 1, 64, 192);
+      if (p >= 2) store_xt_row(p - 2, 64, 192);
     }
     __syncthreads();
     for (int t = p + 1 + wave; t < P; t += 4) {
@@ -170,16 +194,10 @@ chol_inv_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __rest
     for (int jt = wave; jt < P - 1; jt += 4) inverse_tile(P - 1, jt);
   __syncthreads();
 
-  // LT(j, i) = L(i, j) and XT(j, i) = X(i, j), both upper triangular, ld ldo:
-  // thread t writes entry t % 128 of output columns t / 128, +2, +4, ...
-#pragma unroll 16
-  for (int u = 0; u < kCB / 2; ++u) {
-    const int i = rj + 2 * u, j = ri;
-    if (i < b && j < b) {
-      LT[j + (int64_t)i * ldo] = (i >= j) ? sA[i * kCLD + j] : 0.0;
-      XT[j + (int64_t)i * ldo] = (i > j) ? sA[j * kCLD + i] : ((i == j) ? sD[i] : 0.0);
-    }
-  }
+  // What the loop has not written: L's last panel and X's last two block rows.
+  store_lt_panel(P - 1, 0, 256);
+  if (P >= 2) store_xt_row(P - 2, 0, 256);
+  store_xt_row(P - 1, 0, 256);
   __syncthreads();
   if (tid == 0 && bad) {
     status[1] = blk;

@@ -469,9 +469,14 @@ bool dma_eligible(bool ta, int64_t M, int64_t K, const double* A, int64_t lda, c
 }
 
 // Tile shape: the largest that still occupies every CU (one 128 x 128
-// workgroup per CU, two of the 64-wide shapes), else the smallest.
-void pick_tile(bool ta, int64_t M, int64_t N, int nsplit, int* mt, int* nt) {
+// workgroup per CU, two of the 64-wide shapes), else the smallest.  A
+// triangular right factor (tri) takes 64-wide column tiles: the reduction of
+// column tile n0 stops at n0 + 64, so the exact zeros skipped grow from a
+// quarter to three eighths of the product, and twice as many workgroups
+// balance the uneven lengths.
+void pick_tile(bool ta, int64_t M, int64_t N, int nsplit, int* mt, int* nt, bool tri = false) {
   const bool bigM = M > 64, bigN = N > 64;
+  if (tri && !ta && bigM && bigN) { *mt = 128; *nt = 64; return; }
   if (bigM && bigN) {
     const int64_t need = ta ? 512 : 256;
     if (tiles_for(M, N, 128, 128) * nsplit >= need) { *mt = 128; *nt = 128; return; }
@@ -484,7 +489,7 @@ void pick_tile(bool ta, int64_t M, int64_t N, int nsplit, int* mt, int* nt) {
 }
 
 Plan plan_gemm(bool ta, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B, int64_t ldb,
-               bool allow_split, size_t part_cap, bool sym = false) {
+               bool allow_split, size_t part_cap, bool sym = false, bool tri = false) {
   Plan p;
   p.dma = dma_eligible(ta, M, K, A, lda, B, ldb);
   const int kt = p.dma ? kDmaKT : kKT;
@@ -551,7 +556,7 @@ Plan plan_gemm(bool ta, int64_t M, int64_t N, int64_t K, const double* A, int64_
     p.nsplit = (int)((K + p.kchunk - 1) / p.kchunk);
   }
   if (p.dma) {
-    pick_tile(ta, M, N, p.nsplit, &p.mt, &p.nt);
+    pick_tile(ta, M, N, p.nsplit, &p.mt, &p.nt, tri);
   } else {
     p.mt = M > 64 ? 128 : 64;
     p.nt = N > 64 ? 128 : 64;
@@ -650,7 +655,7 @@ hipError_t gemm_nn(Role role, int64_t M, int64_t N, int64_t K, double alpha, con
                    double flops) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (!ld_ok(lda) || !ld_ok(ldb)) return hipErrorInvalidValue;
-  const Plan p = plan_gemm(false, M, N, K, A, lda, B, ldb, false, 0);
+  const Plan p = plan_gemm(false, M, N, K, A, lda, B, ldb, false, 0, false, role == ROLE_TRSM || role == ROLE_SMALL);
   const double bytes = 8.0 * ((double)K * M + (double)K * N + (double)M * N * (beta != 0.0 ? 2.0 : 1.0));
   const int slot = prof_begin(s);
   hipError_t e;
