@@ -72,8 +72,12 @@ def test_n512_uniform_factor_and_solve(b, seed):
 
 
 @pytest.mark.parametrize("q,r,b", [(300, 200, 64), (129, 129, 128), (1000, 70, 32), (7, 5, 2), (40, 33, 1),
-                                   (257, 256, 128), (520, 520, 100), (64, 64, 64), (1, 1, 1), (5000, 130, 128)])
+                                   (257, 256, 128), (520, 520, 100), (64, 64, 64), (1, 1, 1), (5000, 130, 128),
+                                   (600, 400, 96), (2000, 300, 80)])
 def test_ragged_and_edge_shapes(q, r, b):
+    """Includes widths 80 and 96 (multiples of 16 above 64): the products by
+    the triangular factors then take 64-wide column tiles with a ragged last
+    tile, and the last block is narrower than b."""
     Y = inputs.uniform_matrix(q, r, seed=q + r + b)
     Qg, Rg, info, flags = _factor(Y, b)
     _compare(Y, b, Qg, Rg, info, flags)
