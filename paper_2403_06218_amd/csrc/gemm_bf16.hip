@@ -32,6 +32,7 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
 typedef __attribute__((address_space(3))) void lds_void;
 typedef unsigned char fp8_t;  // OCP E4M3 byte
 
@@ -219,7 +220,7 @@ gemm_bf16_kernel(int64_t M, int64_t N, int64_t K, float alpha, const __bf16* __r
 // one stage ahead; the two rings fill the 160 KiB of LDS.
 //
 // E is __bf16 (v_mfma_f32_16x16x32_bf16, 64 k per stage) or fp8 (OCP E4M3
-// bytes, v_mfma_f32_16x16x32_fp8_fp8, 128 k per stage); both give 128 bytes
+// bytes, v_mfma_scale_f32_16x16x128_f8f6f4, 128 k per stage); both give 128 bytes
 // per column per stage, so the LDS layout is the same.  rs / cs (may be
 // NULL) multiply accumulator row m / column n before alpha: the inverse
 // power-of-two scales of the FP8 operands.
@@ -313,21 +314,31 @@ gemm_lp_wide_kernel(int64_t M, int64_t N, int64_t K, float alpha, const E* __res
     const char* cA = slotA(sa);
     const char* cB = slotB(sb);
     if constexpr (F8) {
-      // k-step h covers bytes 32 h .. 32 h + 31 of each column; lane group lg
-      // supplies bytes 32 h + 8 lg .. + 7: half of chunk 2 h + lg / 2.
+      // One v_mfma_scale_f32_16x16x128_f8f6f4 (E4M3 operands, unit scales)
+      // per tile and stage, a quarter of the instructions of the 16x16x32
+      // form at twice its rate.  Lane group lg supplies, for each 32-k
+      // quarter q, bytes 32 q + 8 lg .. + 7 of its row of A and column of B
+      // (half of chunk 2 q + lg / 2): A and B share that k order, which is
+      // all the product needs.
+      auto frag = [&](const char* base, int x) {
+        v8i f;
 #pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        const int c = 2 * h + (lg >> 1), sub = 8 * (lg & 1);
-        long af[SM], bf[SN];
+        for (int q = 0; q < 4; ++q) {
+          const long w = *(const long*)(base + chunk_off(2 * q + (lg >> 1), x) + 8 * (lg & 1));
+          f[2 * q] = (int)w;
+          f[2 * q + 1] = (int)(w >> 32);
+        }
+        return f;
+      };
+      v8i bf[SN];
 #pragma unroll
-        for (int i = 0; i < SM; ++i) af[i] = *(const long*)(cA + chunk_off(c, wm * WTM + i * 16 + li) + sub);
+      for (int j = 0; j < SN; ++j) bf[j] = frag(cB, wn * WTN + j * 16 + li);
 #pragma unroll
-        for (int j = 0; j < SN; ++j) bf[j] = *(const long*)(cB + chunk_off(c, wn * WTN + j * 16 + li) + sub);
+      for (int i = 0; i < SM; ++i) {
+        const v8i af = frag(cA, wm * WTM + i * 16 + li);
 #pragma unroll
-        for (int i = 0; i < SM; ++i)
-#pragma unroll
-          for (int j = 0; j < SN; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(af[i], bf[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < SN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(af, bf[j], acc[i][j], 0, 0, 0, 127, 0, 127);
       }
     } else {
 #pragma unroll
