@@ -166,3 +166,18 @@ def test_large_factor_and_refinement_properties(prec):
     r = (Y @ x - rhs).abs().max()
     hpl = float(r / (Y.abs().sum(dim=1).max() * x.abs().max() * n * EPS))
     assert hpl < 16, hpl
+
+
+@pytest.mark.parametrize("prec", [cqr.PREC_BF16, cqr.PREC_FP8])
+@pytest.mark.parametrize("n,b", [(1024, 256), (512, 64)])
+def test_mixed_permutation_bit_exact(prec, n, b):
+    """Permutation input: 0/1 entries are exact in BF16 and FP8, every
+    projection P^T Y_j is exactly 0 (a product that paired A and B entries of
+    different k would make some 1) and every Gram exactly I, so Q = Y and
+    R = I to the bit in both low-precision forms, wide and narrow tiles."""
+    Y = np.asfortranarray(np.eye(n)[:, np.random.default_rng(n + b).permutation(n)])
+    Q, R, info = cqr.qr_mixed(to_dev(Y), b, prec=prec)
+    torch.cuda.synchronize()
+    assert info == 0
+    assert np.array_equal(_host32(Q), Y)
+    assert np.array_equal(_host32(R), np.eye(n))
