@@ -16,6 +16,7 @@ marshals numpy arrays through ctypes.  Functions:
 * ``cgs_cqr2(Q, P)``         Algorithm 5 alone.
 * ``chol(W)``, ``trsm_rlt``  the POTRF / TRSM building blocks of Table 1.
 * ``qr_solve``, ``qr_solve_grad``  x = R^{-1} Q^T b and its adjoint.
+* ``check_invariants``       the loop invariants I1-I4 of Algorithm 3.
 """
 from __future__ import annotations
 
@@ -62,6 +63,7 @@ def _load():
             "ora_householder_qr": ([i64, i64, dp, i64, dp, i64, dp, i64], i32),
             "ora_qr_solve": ([i64, dp, i64, dp, i64, dp, dp], i32),
             "ora_qr_solve_grad": ([i64, dp, i64, dp, i64, dp, dp, dp, i64, dp], i32),
+            "ora_check_invariants": ([i64, i64, i64, dp, i64, dp, i64, dp, i64, dp], None),
             "ora_num_threads": ([], i32),
         }
         for name, (args, res) in sig.items():
@@ -145,6 +147,21 @@ def cgs_qr(Y, b: int, variant: int = 0, check_invariants: bool = False):
     out = {"Q": Q, "R": R, "info": int(info[0]), "block_flags": flags[:k].copy()}
     if inv is not None:
         out["inv"] = inv
+    return out
+
+
+def check_invariants(Y0, Q, R, J: int):
+    """Loop invariants of Algorithm 3 with J finished columns: returns
+    [I1, I2, I3, I4] = [||Q_J^T Q_J - I||_F / (q eps),
+    ||Y_J - Q_J R_J||_F / (q eps ||Y_J||_F), 1 if R_J is not upper triangular
+    with a non-negative diagonal, 1 if a column at or after J differs from Y0
+    in any bit]."""
+    Y0 = _f64(Y0)
+    Q = _f64(Q)
+    R = _f64(R)
+    q, r = Q.shape
+    out = np.zeros(4)
+    _load().ora_check_invariants(q, r, J, _p(Y0), max(q, 1), _p(Q), max(q, 1), _p(R), max(r, 1), _p(out))
     return out
 
 

@@ -256,10 +256,13 @@ static int cgs2_columns(int64_t q, int64_t c0, int64_t w, double* Q, int64_t ldq
  *   I3  R[:J, :J] upper triangular with exact zeros below the diagonal and
  *       a diagonal > 0 (or == 0 exactly for a dependent column)      -> 0 / 1
  *   I4  Q[:, J:] bit-identical to Y[:, J:]                             -> 0 / 1
- * out[0..3] receives the running maxima of I1, I2 and the violation flags.
+ * Y0 is the input with leading dimension ldy0 (>= q).  out[0..3] receives the
+ * running maxima of I1, I2 and the violation flags (the caller zeroes it
+ * before the first call).  Exported so that tests can feed it factorizations
+ * with planted violations.
  */
-static void check_invariants(int64_t q, int64_t r, int64_t J, const double* Y0, const double* Q, int64_t ldq,
-                             const double* R, int64_t ldr, double* out) {
+void ora_check_invariants(int64_t q, int64_t r, int64_t J, const double* Y0, int64_t ldy0, const double* Q,
+                          int64_t ldq, const double* R, int64_t ldr, double* out) {
   const double eps = 0x1p-52;
   double orth = 0.0, rec = 0.0, ynorm = 0.0;
   for (int64_t j = 0; j < J; ++j)
@@ -273,9 +276,9 @@ static void check_invariants(int64_t q, int64_t r, int64_t J, const double* Y0, 
     for (int64_t i = 0; i < q; ++i) {
       double acc = 0.0;
       for (int64_t p = 0; p <= j; ++p) acc += AT(Q, i, p, ldq) * AT(R, p, j, ldr);
-      double d = AT(Y0, i, j, q) - acc;
+      double d = AT(Y0, i, j, ldy0) - acc;
       rec += d * d;
-      ynorm += AT(Y0, i, j, q) * AT(Y0, i, j, q);
+      ynorm += AT(Y0, i, j, ldy0) * AT(Y0, i, j, ldy0);
     }
   double i1 = sqrt(orth) / ((double)q * eps);
   double i2 = (ynorm > 0.0) ? sqrt(rec) / ((double)q * eps * sqrt(ynorm)) : 0.0;
@@ -287,7 +290,7 @@ static void check_invariants(int64_t q, int64_t r, int64_t J, const double* Y0, 
   }
   for (int64_t j = J; j < r; ++j)
     for (int64_t i = 0; i < q; ++i)
-      if (memcmp(&AT(Q, i, j, ldq), &AT(Y0, i, j, q), sizeof(double)) != 0) bad4 = 1;
+      if (memcmp(&AT(Q, i, j, ldq), &AT(Y0, i, j, ldy0), sizeof(double)) != 0) bad4 = 1;
   if (i1 > out[0]) out[0] = i1;
   if (i2 > out[1]) out[1] = i2;
   if (bad3) out[2] = 1.0;
@@ -350,7 +353,7 @@ int ora_cgs_qr(int64_t q, int64_t r, int64_t b, double* Y, int64_t ldy, double* 
       if (info && *info == 0) *info = (int32_t)(blk + 1);
     }
     if (block_flags) block_flags[blk] = flags;
-    if (inv) check_invariants(q, r, s + w, Y0, Y, ldy, R, ldr, inv);
+    if (inv) ora_check_invariants(q, r, s + w, Y0, q, Y, ldy, R, ldr, inv);
   }
   free(save);
   free(Y0);

@@ -1,6 +1,12 @@
-"""Build the HIP libraries in-tree: lib/libcqr.so and lib/libcqr_synth.so (gfx950)."""
+"""Build the HIP libraries in-tree: lib/libcqr.so and lib/libcqr_synth.so (gfx950).
+
+Every source is compiled to its own object in parallel (no relocatable device
+code: each file's kernels are self-contained, only host functions cross files),
+then the objects are linked into the shared library.
+"""
 from __future__ import annotations
 
+import concurrent.futures as cf
 import os
 import subprocess
 import sys
@@ -8,43 +14,58 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "lib")
+OBJDIR = os.path.join(LIBDIR, "obj")
 ROOT = os.path.dirname(PKG)
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 # Packed FP32 instructions are disabled for every HIP source: some of their
 # forms have given intermittently wrong results on gfx950, with no error.
-HIP_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
+HIP_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-I" + os.path.join(ROOT, "include")]
 
 LIBS = {
-    "libcqr.so": ["cqr.hip", "gemm_f64.hip", "chol_f64.hip", "gemm_bf16.hip", "mixed.hip", "batched.hip", "adjoint.hip", "trsv.hip", "tall.hip"],
+    "libcqr.so": ["cqr.hip", "gemm_f64.hip", "chol_f64.hip", "gemm_bf16.hip", "mixed.hip", "batched.hip",
+                  "adjoint.hip", "trsv.hip", "tall.hip", "fallback.hip", "noalloc.hip", "svd.hip", "spmm.hip"],
     "libcqr_synth.so": ["synth.hip"],
 }
 
+# hipcc's host pass reports the disabled packed-fp32 feature as unknown; that is expected.
+_NOISE = "'-packed-fp32-ops' is not a recognized feature"
 
-def _compile(out: str, sources: list[str], verbose: bool) -> None:
-    os.makedirs(LIBDIR, exist_ok=True)
-    target = os.path.join(LIBDIR, out)
-    tmp = target + ".tmp%d" % os.getpid()
-    cmd = [HIPCC] + HIP_FLAGS + ["-o", tmp] + [os.path.join(CSRC, s) for s in sources]
+
+def _run(cmd: list[str], what: str, verbose: bool) -> None:
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
-    # hipcc's host pass reports the disabled packed-fp32 feature as unknown; that is expected.
-    noise = "'-packed-fp32-ops' is not a recognized feature"
-    err = "\n".join(l for l in res.stderr.splitlines() if noise not in l)
+    err = "\n".join(l for l in res.stderr.splitlines() if _NOISE not in l)
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed for %s:\n%s" % (out, err))
+        raise RuntimeError("hipcc failed for %s:\n%s" % (what, err))
     if verbose and err.strip():
         print(err, file=sys.stderr)
-    os.replace(tmp, target)
 
 
-def build(verbose: bool = False) -> None:
-    for out, sources in LIBS.items():
-        _compile(out, sources, verbose)
+def _object(src: str, verbose: bool) -> str:
+    obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+    tmp = obj + ".tmp%d" % os.getpid()
+    _run([HIPCC] + HIP_FLAGS + ["-c", "-o", tmp, os.path.join(CSRC, src)], src, verbose)
+    os.replace(tmp, obj)
+    return obj
+
+
+def build(verbose: bool = False, jobs: int | None = None) -> None:
+    os.makedirs(OBJDIR, exist_ok=True)
+    sources = [s for srcs in LIBS.values() for s in srcs if os.path.exists(os.path.join(CSRC, s))]
+    jobs = jobs or min(8, len(sources), max(1, (os.cpu_count() or 1)))
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        objs = dict(zip(sources, ex.map(lambda s: _object(s, verbose), sources)))
+    for out, srcs in LIBS.items():
+        target = os.path.join(LIBDIR, out)
+        tmp = target + ".tmp%d" % os.getpid()
+        _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + [objs[s] for s in srcs if s in objs],
+             out, verbose)
+        os.replace(tmp, target)
 
 
 if __name__ == "__main__":

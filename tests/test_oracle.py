@@ -255,13 +255,66 @@ def test_loop_invariants_every_block(q, r, b, seed):
     assert i3 == 0 and i4 == 0
 
 
+def _clean_partial(q=24, r=20, b=4, blocks=3, seed=5):
+    """A factorization stopped after `blocks` column blocks of Algorithm 3:
+    the first J = blocks*b columns of Q and R finished, the rest of Q still Y."""
+    Y = inputs.uniform_matrix(q, r, seed)
+    J = blocks * b
+    out = oracle.cgs_qr(Y[:, :J], b)
+    Q = Y.copy(order="F")
+    Q[:, :J] = out["Q"]
+    R = np.zeros((r, r), order="F")
+    R[:J, :J] = out["R"]
+    return Y, Q, R, J
+
+
+def test_invariant_check_clean_partial_factorization():
+    Y, Q, R, J = _clean_partial()
+    i1, i2, i3, i4 = oracle.check_invariants(Y, Q, R, J)
+    assert i1 < 16 and i2 < 16 and i3 == 0 and i4 == 0
+
+
 def test_invariant_check_detects_planted_error():
-    """The I4 check is live: the oracle's own invariant code flags a column that
-    changed before its block was reached (planted on the CPU in a copy)."""
+    """Each invariant fires on a violation planted (on the CPU) in an otherwise
+    clean partial factorization, and only that one: I1 a non-orthogonal
+    column, I2 a Q R that misses Y, I3 a sub-diagonal entry or a negative
+    diagonal of R, I4 one flipped bit in a column not yet reached."""
+    Y, Q, R, J = _clean_partial()
+    # I1: column 1 of Q and row 1 of R rescaled together (Q R unchanged).
+    Q1, R1 = Q.copy(order="F"), R.copy(order="F")
+    Q1[:, 1] *= 1.0 + 1e-9
+    R1[1, :] /= 1.0 + 1e-9
+    inv = oracle.check_invariants(Y, Q1, R1, J)
+    assert inv[0] > 1e3 and inv[1] < 16 and inv[2] == 0 and inv[3] == 0, inv
+    # I2: one off-diagonal entry of R moved (Q still orthonormal).
+    R2 = R.copy(order="F")
+    R2[2, J - 1] += 1e-9
+    inv = oracle.check_invariants(Y, Q, R2, J)
+    assert inv[0] < 16 and inv[1] > 1e3 and inv[2] == 0 and inv[3] == 0, inv
+    # I3: a tiny nonzero below the diagonal (Q R moves by far less than eps).
+    R3 = R.copy(order="F")
+    R3[J - 1, 2] = 1e-300
+    inv = oracle.check_invariants(Y, Q, R3, J)
+    assert inv[0] < 16 and inv[1] < 16 and inv[2] == 1 and inv[3] == 0, inv
+    # I3: a negative diagonal entry, with the Q column negated (Q R unchanged).
+    Q4, R4 = Q.copy(order="F"), R.copy(order="F")
+    Q4[:, 3] = -Q4[:, 3]
+    R4[3, :] = -R4[3, :]
+    inv = oracle.check_invariants(Y, Q4, R4, J)
+    assert inv[0] < 16 and inv[1] < 16 and inv[2] == 1 and inv[3] == 0, inv
+    # I4: the lowest bit of one entry of a later column flipped.
+    Q5 = Q.copy(order="F")
+    col = Q5[:, J + 2].copy()
+    col.view(np.uint64)[7] ^= np.uint64(1)
+    Q5[:, J + 2] = col
+    inv = oracle.check_invariants(Y, Q5, R, J)
+    assert inv[0] < 16 and inv[1] < 16 and inv[2] == 0 and inv[3] == 1, inv
+
+
+def test_invariants_hold_through_the_fallback():
+    """A rank-deficient block forces the CGS2 fallback; the invariants still hold
+    after every block (the dependent column is zero with R_jj = 0)."""
     Y = inputs.uniform_matrix(20, 20, 5)
-    out = oracle.cgs_qr(Y, 4, check_invariants=True)
-    assert out["inv"][3] == 0
-    # A rank-deficient block forces the fallback; the invariants still hold.
     Y2 = Y.copy()
     Y2[:, 9] = Y2[:, 8]
     out2 = oracle.cgs_qr(Y2, 4, check_invariants=True)
