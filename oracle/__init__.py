@@ -16,7 +16,10 @@ marshals numpy arrays through ctypes.  Functions:
 * ``cgs_cqr2(Q, P)``         Algorithm 5 alone.
 * ``chol(W)``, ``trsm_rlt``  the POTRF / TRSM building blocks of Table 1.
 * ``qr_solve``, ``qr_solve_grad``  x = R^{-1} Q^T b and its adjoint.
+* ``orth_against_fb``        Algorithm 5 (or 4) with the CGS2 fallback.
 * ``check_invariants``       the loop invariants I1-I4 of Algorithm 3.
+
+``oracle.svd`` holds the truncated-SVD drivers (RandSVD, LancSVD) built on these.
 """
 from __future__ import annotations
 
@@ -64,6 +67,7 @@ def _load():
             "ora_qr_solve": ([i64, dp, i64, dp, i64, dp, dp], i32),
             "ora_qr_solve_grad": ([i64, dp, i64, dp, i64, dp, dp, dp, i64, dp], i32),
             "ora_check_invariants": ([i64, i64, i64, dp, i64, dp, i64, dp, i64, dp], None),
+            "ora_orth_against_fb": ([i64, i64, i64, dp, i64, dp, i64, dp, i64], i32),
             "ora_num_threads": ([], i32),
         }
         for name, (args, res) in sig.items():
@@ -148,6 +152,23 @@ def cgs_qr(Y, b: int, variant: int = 0, check_invariants: bool = False):
     if inv is not None:
         out["inv"] = inv
     return out
+
+
+def orth_against_fb(Q, P=None):
+    """Algorithm 5 (Algorithm 4 when P is None or empty) with the CGS2
+    breakdown fallback.  Returns (Q, H, R, rc): rc 0, 1 (fallback) or 3
+    (fallback with an exactly dependent column)."""
+    Q = np.asarray(Q, dtype=np.float64)
+    q, w = Q.shape
+    s = 0 if P is None else P.shape[1]
+    X = np.zeros((q, s + w), order="F")
+    if s:
+        X[:, :s] = P
+    X[:, s:] = Q
+    H = np.zeros((max(s, 1), w), order="F")
+    R = np.zeros((w, w), order="F")
+    rc = _load().ora_orth_against_fb(q, s, w, _p(X), max(q, 1), _p(H), max(s, 1), _p(R), max(w, 1))
+    return np.asfortranarray(X[:, s:]), H[:s], R, int(rc)
 
 
 def check_invariants(Y0, Q, R, J: int):

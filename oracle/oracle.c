@@ -245,6 +245,38 @@ static int cgs2_columns(int64_t q, int64_t c0, int64_t w, double* Q, int64_t ldq
   return nzero;
 }
 
+/*
+ * Algorithm 5 with the Section 3 breakdown fallback, for callers that keep
+ * the basis and the block side by side: X holds [P | Q] with P = X[:, 0:s]
+ * (orthonormal columns) and the block Q = X[:, s:s+w].  Q is orthogonalised
+ * against P (H = s x w coefficients, R = w x w triangle, Q_in = P H + Q_out R).
+ * If either Cholesky factorisation breaks down, Q is restored and redone
+ * column by column by CGS2 against P and its own earlier columns (reading R5,
+ * R8 for an exactly dependent column).  s = 0 is Algorithm 4 with the same
+ * fallback.  Returns 0, 1 (fallback taken) or 3 (fallback with a zero column).
+ */
+int ora_orth_against_fb(int64_t q, int64_t s, int64_t w, double* X, int64_t ldx, double* H, int64_t ldh, double* R,
+                        int64_t ldr) {
+  double* save = (double*)malloc((size_t)(q * w + 1) * sizeof(double));
+  for (int64_t c = 0; c < w; ++c) memcpy(&save[c * q], &AT(X, 0, s + c, ldx), (size_t)q * sizeof(double));
+  int rc = ora_cgs_cqr2(q, w, s, &AT(X, 0, s, ldx), ldx, X, ldx, H, ldh, R, ldr, 0);
+  if (rc == 0) {
+    free(save);
+    return 0;
+  }
+  for (int64_t c = 0; c < w; ++c) memcpy(&AT(X, 0, s + c, ldx), &save[c * q], (size_t)q * sizeof(double));
+  const int64_t t = s + w;
+  double* Rt = (double*)calloc((size_t)(t * t), sizeof(double));
+  const int nz = cgs2_columns(q, s, w, X, ldx, Rt, t);
+  for (int64_t c = 0; c < w; ++c) {
+    for (int64_t i = 0; i < s; ++i) AT(H, i, c, ldh) = AT(Rt, i, s + c, t);
+    for (int64_t i = 0; i < w; ++i) AT(R, i, c, ldr) = AT(Rt, s + i, s + c, t);
+  }
+  free(Rt);
+  free(save);
+  return nz > 0 ? 3 : 1;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Loop invariants of Algorithm 3 after a finished column block.             */
 /* ------------------------------------------------------------------------ */

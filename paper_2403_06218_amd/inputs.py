@@ -132,3 +132,37 @@ def packed_vector(sizes, i: int, seed: int, lo: float = -1.0, hi: float = 1.0) -
     o = int(sizes[:i].sum())
     t = np.arange(o, o + int(sizes[i]), dtype=np.uint64)
     return _affine(uniform01(seed, t), lo, hi)
+
+
+def svd_test_sigma(n: int) -> np.ndarray:
+    """Singular values of the dense truncated-SVD benchmark (Sec. 4, dense
+    problems): sigma_i = 10^(15 i / (n/2) - 14) for 1 <= i <= n/2 and 1e-14
+    for the rest, returned in decreasing order (largest 10, at i = n/2)."""
+    h = n // 2
+    i = np.arange(1, h + 1, dtype=np.float64)
+    top = 10.0 ** (15.0 * i / h - 14.0)
+    return np.concatenate([top[::-1], np.full(n - h, 1e-14)])
+
+
+def svd_test_matrix(m: int, n: int, seed: int):
+    """A = X Sigma Y^T (m x n, column-major) with the singular values of
+    ``svd_test_sigma`` and random orthogonal factors.  Y is the Q factor of an
+    n x n Gaussian matrix; X (m x n, m a multiple c of n) stacks c row blocks
+    D_l Z P_l / sqrt(c), with Z the Q factor of another n x n Gaussian matrix,
+    D_l random signs and P_l random column permutations, so that
+    X^T X = I exactly in exact arithmetic and large m stays cheap.  Returns
+    (A, sigma)."""
+    if m % n:
+        raise ValueError("m must be a multiple of n")
+    c = m // n
+    rng = np.random.default_rng(seed)
+    Y, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    Z, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    sig = svd_test_sigma(n)
+    SYt = sig[:, None] * Y.T
+    A = np.empty((m, n), order="F")
+    for l in range(c):
+        d = rng.choice(np.array([-1.0, 1.0]), size=n)
+        perm = rng.permutation(n)
+        A[l * n:(l + 1) * n, :] = (d[:, None] * Z[:, perm]) @ SYt / np.sqrt(c)
+    return A, sig
