@@ -291,8 +291,9 @@ def bench_tall(cqr, torch, K: int, W: int, seed: int) -> dict:
             cqr.qr(Ys[i], b, R=R, work=work)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        infos = [cqr.qr(Ys[W + i], b, R=R, work=work)[2] for i in range(K)]
+        infos = [cqr.qr_async(Ys[W + i], b, R=R, work=work)[2] for i in range(K)]
         torch.cuda.synchronize()
+        infos = [int(v[0]) for v in infos]
         ms = (time.perf_counter() - t0) / K * 1e3
         Yp = Ys[0]
         Yp.copy_(Y0)
@@ -362,7 +363,7 @@ def bench_fp64(args, torch, cqr, costmodel, inputs):
     torch.cuda.synchronize()
 
     def step(i):
-        Q, Rr, info, flags = cqr.qr(Ys[i], b, R=R, work=work)
+        Q, Rr, info, flags = cqr.qr_async(Ys[i], b, R=R, work=work)
         x = cqr.solve(Q, Rr, rhs, work=swork)
         return info, x
 
@@ -382,6 +383,7 @@ def bench_fp64(args, torch, cqr, costmodel, inputs):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     cqr.prof_enable(False)
+    infos = [int(v[0]) for v in infos]
 
     flops_step = costmodel.ca3(b, n, n) + costmodel.solve_flops(n)
     ms_step = 1e3 * elapsed / K

@@ -22,7 +22,8 @@
  *     C signature) is invalid; CQR_ERR_* below otherwise.  On an argument error
  *     nothing is enqueued.
  *   - Outputs of type int32_t* marked "host" are written by the host after the
- *     call has synchronised the stream.
+ *     call has synchronised the stream; those marked "device" are written by
+ *     the call's kernels, in stream order.
  */
 #ifndef CQR_H
 #define CQR_H
@@ -35,13 +36,18 @@ extern "C" {
 #endif
 
 #define CQR_OK 0
-#define CQR_ERR_UNSUPPORTED (-100) /* valid request this build does not support (b > 128, ld > 4e6) */
+#define CQR_ERR_UNSUPPORTED (-100) /* valid request this build does not support (b > 256, ld > 4e6) */
 #define CQR_ERR_WORKSPACE (-101)   /* work == NULL or work_bytes below the required size     */
 #define CQR_ERR_HIP_BASE (-1000)   /* -1000 - hipError_t: a HIP launch or runtime call failed */
 
 /* Precision forms of cqr_factor_mixed. */
 #define CQR_PREC_BF16 1 /* projections and updates on BF16 MFMA with FP32 accumulation */
 #define CQR_PREC_FP8 2  /* ... on FP8 (OCP E4M3) MFMA, per-column power-of-two scales, FP32 accumulation */
+
+/* info of cqr_factor / cqr_orth / cqr_orth_against when a bounded wait inside
+ * the breakdown fallback was abandoned (its workgroups were not all resident
+ * within cqr_set_wait_limit_us); Q, R and H are then not valid. */
+#define CQR_INFO_WAIT_ABANDONED (-2)
 
 /* Bits of the per-block flags written by cqr_factor. */
 #define CQR_FLAG_FALLBACK 1 /* the block's Cholesky factorisation broke down; redone by CGS2 */
@@ -56,7 +62,8 @@ const char* cqr_version(void);
 /*
  * Bytes of device workspace cqr_factor needs for Y (q x r) and block width b;
  * also valid for cqr_orth (r = b) and cqr_orth_against (r = s + b).
- * Returns -1..-3 for q < 0, r < 0 or r > q, b < 1 or b > 128.
+ * Returns -1..-3 for q < 0, r < 0 or r > q, b < 1; CQR_ERR_UNSUPPORTED for
+ * b > 256.
  */
 int cqr_workspace_size(int64_t q, int64_t r, int64_t b, size_t* bytes);
 
@@ -65,44 +72,61 @@ int cqr_workspace_size(int64_t q, int64_t r, int64_t b, size_t* bytes);
  * triangular with positive diagonal.  Q overwrites Y in place.
  *   Y, ldy   in: Y; out: Q.  ldy >= max(1, q).
  *   R, ldr   out: r x r upper triangular (strictly lower part set to 0).
- *   b        block width, 1 <= b <= 128; the last block has width r - (k-1) b
+ *   b        block width, 1 <= b <= 256; the last block has width r - (k-1) b
  *            with k = ceil(r / b).  Block 1 is orthogonalised by CholeskyQR2
  *            (Algorithm 4); block j >= 2 by CGS-CQR2 (Algorithm 5) against the
  *            s = (j-1) b columns before it, its projection written to
  *            R[0:s, block j] and its triangular factor to the diagonal block.
+ *            Blocks wider than 128 factor their Gram matrix as a 2 x 2 block.
  *   work     device workspace of work_bytes >= cqr_workspace_size(q, r, b).
- *   info     host, may be NULL: 0, or the 1-based index of the first block
- *            whose Cholesky factorisation broke down (a pivot that is not > 0,
- *            NaN included).  Such a block is restored and redone column by
+ *   info     device int32, may be NULL: 0, or the 1-based index of the first
+ *            block whose Cholesky factorisation broke down (a pivot that is not
+ *            > 0, NaN included).  Such a block is restored and redone column by
  *            column by classical Gram-Schmidt with re-orthogonalisation (CGS2),
  *            which the paper's Section 3 prescribes as the fallback; the
- *            result is still a QR factorisation.
- *   block_flags  host, may be NULL, length k: CQR_FLAG_* bits per block.
- *            A column whose remainder after projection has zero norm gets a
- *            zero Q column and R_jj = 0 (CQR_FLAG_ZERO_COL).
- * The call returns after the stream has finished the factorisation (it
- * synchronises once at the end to learn whether a fallback is needed).
+ *            result is still a QR factorisation.  CQR_INFO_WAIT_ABANDONED if a
+ *            bounded wait of that fallback was abandoned (results not valid).
+ *   block_flags  device int32, may be NULL, length k: CQR_FLAG_* bits per
+ *            block.  A column whose remainder after projection has zero norm
+ *            gets a zero Q column and R_jj = 0 (CQR_FLAG_ZERO_COL).
+ * Asynchronous: every step, the fallback decision included, runs in kernels
+ * enqueued on `stream`; nothing is read back to the host, so the call can be
+ * captured in a hipGraph.  info and block_flags are valid once the stream
+ * has reached the end of the call.  Calls sharing a workspace must not
+ * overlap.
  */
 int cqr_factor(int64_t q, int64_t r, int64_t b, double* Y, int64_t ldy, double* R, int64_t ldr, void* work,
                size_t work_bytes, int32_t* info, int32_t* block_flags, void* stream);
 
 /*
- * CholeskyQR2 (Algorithm 4): Q (q x b, q >= b) in place -> orthonormal Q and
- * R (b x b upper triangular) with Q_in = Q_out R.  info (host, may be NULL):
- * 0, or 1 if the fallback to CGS2 was taken.  Synchronises like cqr_factor.
+ * CholeskyQR2 (Algorithm 4): Q (q x b, q >= b, b <= 256) in place ->
+ * orthonormal Q and R (b x b upper triangular) with Q_in = Q_out R.  info
+ * (device int32, may be NULL): 0, 1 if the fallback to CGS2 was taken, or
+ * CQR_INFO_WAIT_ABANDONED.  Asynchronous like cqr_factor.
  */
 int cqr_orth(int64_t q, int64_t b, double* Q, int64_t ldq, double* R, int64_t ldr, void* work, size_t work_bytes,
              int32_t* info, void* stream);
 
 /*
- * CGS-CQR2 (Algorithm 5): orthogonalise Q (q x b) against P (q x s, whose
- * columns are assumed orthonormal) ->  Q_in = P H + Q_out R, P^T Q_out = 0,
- * Q_out^T Q_out = I.  H (s x b, ldh >= max(1, s)) and R (b x b) are outputs.
- * Q and P must not overlap.  q >= s + b.  info as for cqr_orth.
+ * CGS-CQR2 (Algorithm 5): orthogonalise Q (q x b, b <= 256) against P (q x s,
+ * whose columns are assumed orthonormal) ->  Q_in = P H + Q_out R,
+ * P^T Q_out = 0, Q_out^T Q_out = I.  H (s x b, ldh >= max(1, s)) and R (b x b)
+ * are outputs.  Q and P must not overlap.  q >= s + b.  info as for cqr_orth
+ * (device); asynchronous like cqr_factor.
  */
 int cqr_orth_against(int64_t q, int64_t b, int64_t s, double* Q, int64_t ldq, const double* P, int64_t ldp,
                      double* H, int64_t ldh, double* R, int64_t ldr, void* work, size_t work_bytes, int32_t* info,
                      void* stream);
+
+/*
+ * Bound of every bounded wait inside the library's kernels (the grid barriers
+ * of the breakdown fallback, the look-back of the back substitution), in
+ * microseconds of device time; default 10 s.  Past it a kernel stops waiting,
+ * finishes without hanging and reports the abandoned wait (info
+ * CQR_INFO_WAIT_ABANDONED, or the status of cqr_solve).  Applies to launches
+ * made after the call.  Returns -1 for us < 0.
+ */
+int cqr_set_wait_limit_us(int64_t us);
 
 /* Bytes of device workspace cqr_solve needs for order n (returns -1 for n < 0). */
 int cqr_solve_workspace_size(int64_t n, size_t* bytes);
@@ -116,12 +140,16 @@ int cqr_solve_workspace_size(int64_t n, size_t* bytes);
  *            inverses of R's 64 x 64 diagonal blocks and the counters of the
  *            one-launch substitution (cleared by the call itself).  Calls that
  *            share a workspace must not overlap.
+ *   status   device int32, may be NULL (not written when n == 0): 0, or 1 if
+ *            the back substitution abandoned a bounded wait for a finished
+ *            row block (see cqr_set_wait_limit_us); x is then not valid, and
+ *            the blocks from the abandoned one upwards are NaN.
  * A zero diagonal entry of R (a dependent column) yields Inf/NaN entries.
  * Asynchronous: enqueues the work on `stream` and returns (capturable in a
  * hipGraph: kernels only).
  */
 int cqr_solve(int64_t n, const double* Q, int64_t ldq, const double* R, int64_t ldr, double* x, void* work,
-              size_t work_bytes, void* stream);
+              size_t work_bytes, int32_t* status, void* stream);
 
 /*
  * Low-precision form of cqr_factor (not in the paper, which computes in IEEE
@@ -224,6 +252,119 @@ int cqr_batched_plan_set(int dtype, int32_t nbuckets, const int32_t* hi, const i
 int cqr_batched_solve_backward(int64_t count, int dtype, const int32_t* n, void* const* Q, const int32_t* ldq,
                                void* const* R, const int32_t* ldr, void* const* x, void* const* g, void* const* dA,
                                const int32_t* ldda, void* const* db, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Truncated SVD (Section 2): RandSVD (Algorithm 1) and LancSVD (Algorithm 2)
+ * of an m x n matrix A, on the factorisations above.  A is dense (column-major
+ * FP64) or sparse (CSR, with its transpose as a second CSR).  Every step runs
+ * in the library's kernels on `stream` (asynchronous, no host round trip):
+ * the products with A, the orthogonalisations (Algorithms 3-5 with the
+ * device-side CGS2 fallback) and the small SVD (one-sided Jacobi, one
+ * workgroup).  The random start blocks are inputs.  r <= 256, r a multiple of
+ * b, b <= 256; LancSVD also needs m >= r + b (it forms Qbar_{k+1}).
+ * ------------------------------------------------------------------------ */
+#define CQR_SVD_LANCZOS 0
+#define CQR_SVD_RANDOMIZED 1
+#define CQR_SVD_SPARSE 2 /* OR'ed into `method`: workspace of the CSR entry points */
+
+/* Bytes of device workspace of cqr_lancsvd / cqr_randsvd (method
+ * CQR_SVD_LANCZOS or CQR_SVD_RANDOMIZED, | CQR_SVD_SPARSE for the _csr forms). */
+int cqr_svd_workspace_size(int method, int64_t m, int64_t n, int64_t r, int64_t b, size_t* bytes);
+
+/*
+ * LancSVD (Algorithm 2): block Golub-Kahan-Lanczos with full orthogonalisation
+ * of both bases and the basic restart, p restart cycles of k = r / b blocks.
+ *   A, lda   m x n, column-major.
+ *   Q1, ldq  m x b start block (S1 orthonormalises it by Algorithm 4).
+ *   U, ldu   out: m x r left singular vectors (U = Pbar_k Ubar, S9).
+ *   sigma    out: r singular values of B_k, decreasing.
+ *   V, ldv   out: n x r right singular vectors (V = P_k Vbar, S8).
+ *   info     device int32, may be NULL: the number of orthogonalisations that
+ *            took the CGS2 fallback, or CQR_INFO_WAIT_ABANDONED.
+ * B_k carries L_i = (R factor of S3)^T on its diagonal blocks and the R factor
+ * of S5 below them.
+ */
+int cqr_lancsvd(int64_t m, int64_t n, const double* A, int64_t lda, int64_t r, int64_t b, int p, const double* Q1,
+                int64_t ldq, double* U, int64_t ldu, double* sigma, double* V, int64_t ldv, int32_t* info,
+                void* work, size_t work_bytes, void* stream);
+
+/*
+ * RandSVD (Algorithm 1): p steps of randomized subspace iteration from the
+ * n x r start block Q0 (ldq >= n), CGS-QR (Algorithm 3, block width b) of
+ * A Q (m x r) and of A^T Qbar (n x r), the SVD of R_p, U = Qbar_p Vbar,
+ * V = Q_p Ubar.  Outputs and info as for cqr_lancsvd.
+ */
+int cqr_randsvd(int64_t m, int64_t n, const double* A, int64_t lda, int64_t r, int64_t b, int p, const double* Q0,
+                int64_t ldq, double* U, int64_t ldu, double* sigma, double* V, int64_t ldv, int32_t* info,
+                void* work, size_t work_bytes, void* stream);
+
+/*
+ * The same two drivers for a sparse A (m x n, nnz nonzeros, CSR with int32
+ * row pointers and column indices; rows need not be sorted) together with its
+ * transpose (trowptr, tcol, tval: the n x m CSR of A^T, e.g. from
+ * cqr_csr_transpose).  Workspace: cqr_svd_workspace_size(method |
+ * CQR_SVD_SPARSE, ...).
+ */
+int cqr_lancsvd_csr(int64_t m, int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col, const double* val,
+                    const int32_t* trowptr, const int32_t* tcol, const double* tval, int64_t r, int64_t b, int p,
+                    const double* Q1, int64_t ldq, double* U, int64_t ldu, double* sigma, double* V, int64_t ldv,
+                    int32_t* info, void* work, size_t work_bytes, void* stream);
+int cqr_randsvd_csr(int64_t m, int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col, const double* val,
+                    const int32_t* trowptr, const int32_t* tcol, const double* tval, int64_t r, int64_t b, int p,
+                    const double* Q0, int64_t ldq, double* U, int64_t ldu, double* sigma, double* V, int64_t ldv,
+                    int32_t* info, void* work, size_t work_bytes, void* stream);
+
+/*
+ * Small dense SVD B = U diag(sigma) V^T of an r x r matrix (r <= 256) by
+ * one-sided Jacobi in one workgroup (the GESVD step of Algorithms 1 and 2,
+ * which the paper runs on the CPU).  sigma decreasing; columns of U with
+ * sigma = 0 are zero.  sweeps (device int32, may be NULL): sweeps used, or
+ * minus the sweep limit (60) if it was reached before convergence.
+ */
+int cqr_small_svd_workspace_size(int64_t r, size_t* bytes);
+int cqr_small_svd(int64_t r, const double* B, int64_t ldb, double* U, int64_t ldu, double* sigma, double* V,
+                  int64_t ldv, int32_t* sweeps, void* work, size_t work_bytes, void* stream);
+
+/*
+ * Products with A of the truncated SVD on the FP64 MFMA GEMM kernels:
+ * C = alpha A^T B + beta C (trans_a = 1, A: K x M) or alpha A B + beta C
+ * (trans_a = 0, A: M x K); B: K x N, C: M x N.  `work` (may be NULL) holds the
+ * split-K partial sums of the transposed form (cqr_gemm_workspace_size bytes).
+ */
+int cqr_gemm_workspace_size(size_t* bytes);
+int cqr_gemm(int trans_a, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+             const double* B, int64_t ldb, double beta, double* C, int64_t ldc, void* work, size_t work_bytes,
+             void* stream);
+
+/*
+ * Residuals of computed triplets: res[j] = ||A v_j - sigma_j u_j||_2 / sigma_j
+ * for j < count (dense A).  work: m * count doubles.
+ */
+int cqr_svd_residuals(int64_t m, int64_t n, const double* A, int64_t lda, int64_t count, const double* U,
+                      int64_t ldu, const double* sigma, const double* V, int64_t ldv, double* res, void* work,
+                      size_t work_bytes, void* stream);
+
+/*
+ * Sparse products (Table 1, SpMM rows): C = A X (trans = 0; rowptr/col/val
+ * the m x n CSR of A, X n x w, C m x w) or C = A^T X (trans = 1; rowptr/col/
+ * val the n x m CSR of A^T, X m x w, C n x w).  m, n are the dimensions of A
+ * in both cases.  work: cqr_spmm_workspace_size(m, n) bytes (X in row-major
+ * order).  Each row of C sums its nonzeros in storage order (reproducible).
+ */
+int cqr_spmm_workspace_size(int64_t m, int64_t n, size_t* bytes);
+int cqr_spmm(int trans, int64_t m, int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+             const double* val, int64_t w, const double* X, int64_t ldx, double* C, int64_t ldc, void* work,
+             size_t work_bytes, void* stream);
+
+/*
+ * CSR of A^T from the CSR of A (m x n, nnz nonzeros), on the device: column
+ * counts, a prefix sum, a scatter and a sort of every row of A^T by column, so
+ * the result is unique (rows of A^T in increasing order).  trowptr: n + 1
+ * entries; tcol, tval: nnz.  work: cqr_csr_transpose_workspace_size(n) bytes.
+ */
+int cqr_csr_transpose_workspace_size(int64_t n, size_t* bytes);
+int cqr_csr_transpose(int64_t m, int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col, const double* val,
+                      int32_t* trowptr, int32_t* tcol, double* tval, void* work, size_t work_bytes, void* stream);
 
 /*
  * Launch timing.  While enabled, every kernel launch the library makes is

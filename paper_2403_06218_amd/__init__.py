@@ -23,7 +23,8 @@ FLAG_ZERO_COL = 2
 PREC_BF16 = 1
 PREC_FP8 = 2
 
-__all__ = ["colmajor", "workspace_size", "qr", "orth", "orth_against", "solve", "solve_workspace_size", "qr_mixed", "solve_ir",
+__all__ = ["colmajor", "workspace_size", "qr", "qr_async", "orth", "orth_against", "solve", "solve_workspace_size",
+           "set_wait_limit_us", "qr_mixed", "solve_ir",
            "synth_uniform",
            "prof_enable", "prof_reset", "prof_query", "prof_names", "CqrError", "version"]
 
@@ -74,10 +75,16 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
 
 
-def qr(Y: torch.Tensor, b: int, R: torch.Tensor | None = None, work: torch.Tensor | None = None):
-    """CGS-QR of column-major Y (q x r) in place.  Returns (Q, R, info, block_flags).
+def _status(n: int, device) -> torch.Tensor:
+    return torch.zeros(max(n, 1), dtype=torch.int32, device=device)
 
-    Q is Y itself; R is r x r upper triangular (column-major)."""
+
+def qr_async(Y: torch.Tensor, b: int, R: torch.Tensor | None = None, work: torch.Tensor | None = None,
+             info: torch.Tensor | None = None, flags: torch.Tensor | None = None):
+    """CGS-QR of column-major Y (q x r) in place, enqueued on the current
+    stream with no host synchronisation (capturable).  Returns (Q, R, info,
+    flags) with info (1 entry) and flags (one per block) int32 device tensors
+    that the kernels fill."""
     q, r = Y.shape
     ldy = _ld(Y, "Y")
     if R is None:
@@ -87,31 +94,43 @@ def qr(Y: torch.Tensor, b: int, R: torch.Tensor | None = None, work: torch.Tenso
     if work is None:
         work = _workspace(need, Y.device)
     k = -(-r // b) if r else 0
-    flags = (ctypes.c_int32 * max(k, 1))()
-    info = ctypes.c_int32(0)
-    rc = _native.lib().cqr_factor(q, r, b, _ptr(Y), ldy, _ptr(R), ldr, _ptr(work), work.numel(),
-                                  ctypes.byref(info), flags, _stream())
+    info = _status(1, Y.device) if info is None else info
+    flags = _status(k, Y.device) if flags is None else flags
+    rc = _native.lib().cqr_factor(q, r, b, _ptr(Y), ldy, _ptr(R), ldr, _ptr(work), work.numel(), _ptr(info),
+                                  _ptr(flags), _stream())
     _native.check(rc, "cqr_factor")
-    return Y, R, int(info.value), [int(flags[i]) for i in range(k)]
+    return Y, R, info, flags
 
 
-def orth(Q: torch.Tensor, R: torch.Tensor | None = None, work: torch.Tensor | None = None):
-    """CholeskyQR2 of column-major Q (q x b) in place.  Returns (Q, R, info)."""
+def qr(Y: torch.Tensor, b: int, R: torch.Tensor | None = None, work: torch.Tensor | None = None):
+    """CGS-QR of column-major Y (q x r) in place.  Returns (Q, R, info,
+    block_flags) with info and the flags read back to the host (this waits for
+    the stream).  Q is Y itself; R is r x r upper triangular (column-major)."""
+    r = Y.shape[1]
+    k = -(-r // b) if r else 0
+    Q, R, info, flags = qr_async(Y, b, R, work)
+    return Q, R, int(info[0].item()), [int(v) for v in flags[:k].tolist()]
+
+
+def orth(Q: torch.Tensor, R: torch.Tensor | None = None, work: torch.Tensor | None = None, sync: bool = True):
+    """CholeskyQR2 of column-major Q (q x b) in place.  Returns (Q, R, info):
+    info an int (sync=True, waits for the stream) or an int32 device tensor."""
     q, b = Q.shape
     if R is None:
         R = colmajor(b, b, device=Q.device)
     if work is None:
         work = _workspace(workspace_size(q, b, b), Q.device)
-    info = ctypes.c_int32(0)
+    info = _status(1, Q.device)
     rc = _native.lib().cqr_orth(q, b, _ptr(Q), _ld(Q, "Q"), _ptr(R), _ld(R, "R"), _ptr(work), work.numel(),
-                                ctypes.byref(info), _stream())
+                                _ptr(info), _stream())
     _native.check(rc, "cqr_orth")
-    return Q, R, int(info.value)
+    return Q, R, (int(info[0].item()) if sync else info)
 
 
 def orth_against(Q: torch.Tensor, P: torch.Tensor, H: torch.Tensor | None = None, R: torch.Tensor | None = None,
-                 work: torch.Tensor | None = None):
-    """CGS-CQR2: orthogonalise Q (q x b) against P (q x s) in place.  Returns (Q, H, R, info)."""
+                 work: torch.Tensor | None = None, sync: bool = True):
+    """CGS-CQR2: orthogonalise Q (q x b) against P (q x s) in place.  Returns
+    (Q, H, R, info): info an int (sync=True) or an int32 device tensor."""
     q, b = Q.shape
     s = P.shape[1]
     if H is None:
@@ -121,12 +140,17 @@ def orth_against(Q: torch.Tensor, P: torch.Tensor, H: torch.Tensor | None = None
     if work is None:
         work = _workspace(workspace_size(q, s + b, b), Q.device)
     ldh = max(1, H.stride(1)) if s > 0 else 1
-    info = ctypes.c_int32(0)
+    info = _status(1, Q.device)
     rc = _native.lib().cqr_orth_against(q, b, s, _ptr(Q), _ld(Q, "Q"), _ptr(P), _ld(P, "P") if s else max(q, 1),
                                         _ptr(H) if s else ctypes.c_void_p(0), ldh, _ptr(R), _ld(R, "R"),
-                                        _ptr(work), work.numel(), ctypes.byref(info), _stream())
+                                        _ptr(work), work.numel(), _ptr(info), _stream())
     _native.check(rc, "cqr_orth_against")
-    return Q, H, R, int(info.value)
+    return Q, H, R, (int(info[0].item()) if sync else info)
+
+
+def set_wait_limit_us(us: int) -> None:
+    """Bound of the library's bounded device-side waits (microseconds)."""
+    _native.check(_native.lib().cqr_set_wait_limit_us(int(us)), "cqr_set_wait_limit_us")
 
 
 def solve_workspace_size(n: int) -> int:
@@ -136,14 +160,17 @@ def solve_workspace_size(n: int) -> int:
     return int(nb.value)
 
 
-def solve(Q: torch.Tensor, R: torch.Tensor, rhs: torch.Tensor, work: torch.Tensor | None = None) -> torch.Tensor:
-    """x = R^{-1} Q^T rhs (asynchronous on the current stream).  rhs is not modified."""
+def solve(Q: torch.Tensor, R: torch.Tensor, rhs: torch.Tensor, work: torch.Tensor | None = None,
+          status: torch.Tensor | None = None) -> torch.Tensor:
+    """x = R^{-1} Q^T rhs (asynchronous on the current stream).  rhs is not
+    modified.  status (optional int32 device tensor) receives 0, or 1 if the
+    back substitution abandoned a bounded wait (x is then not valid)."""
     n = Q.shape[0]
     x = rhs.clone().contiguous()
     if work is None:
         work = _workspace(solve_workspace_size(n), Q.device)
     rc = _native.lib().cqr_solve(n, _ptr(Q), _ld(Q, "Q"), _ptr(R), _ld(R, "R"), _ptr(x), _ptr(work), work.numel(),
-                                 _stream())
+                                 _ptr(status), _stream())
     _native.check(rc, "cqr_solve")
     return x
 

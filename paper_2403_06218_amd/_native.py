@@ -20,12 +20,13 @@ CQR_SIGNATURES = {
     "cqr_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "cqr_version": ([], ctypes.c_char_p),
     "cqr_workspace_size": ([i64, i64, i64, szp], ctypes.c_int),
-    "cqr_factor": ([i64, i64, i64, vp, i64, vp, i64, vp, ctypes.c_size_t, i32p, i32p, vp], ctypes.c_int),
-    "cqr_orth": ([i64, i64, vp, i64, vp, i64, vp, ctypes.c_size_t, i32p, vp], ctypes.c_int),
-    "cqr_orth_against": ([i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, ctypes.c_size_t, i32p, vp],
+    "cqr_factor": ([i64, i64, i64, vp, i64, vp, i64, vp, ctypes.c_size_t, vp, vp, vp], ctypes.c_int),
+    "cqr_orth": ([i64, i64, vp, i64, vp, i64, vp, ctypes.c_size_t, vp, vp], ctypes.c_int),
+    "cqr_orth_against": ([i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, ctypes.c_size_t, vp, vp],
                          ctypes.c_int),
+    "cqr_set_wait_limit_us": ([i64], ctypes.c_int),
     "cqr_solve_workspace_size": ([i64, szp], ctypes.c_int),
-    "cqr_solve": ([i64, vp, i64, vp, i64, vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
+    "cqr_solve": ([i64, vp, i64, vp, i64, vp, vp, ctypes.c_size_t, vp, vp], ctypes.c_int),
     "cqr_workspace_size_mixed": ([i64, i64, i64, ctypes.c_int, szp], ctypes.c_int),
     "cqr_factor_mixed": ([i64, i64, i64, ctypes.c_int, vp, i64, vp, i64, vp, i64, vp, ctypes.c_size_t, i32p, vp],
                          ctypes.c_int),
@@ -39,6 +40,26 @@ CQR_SIGNATURES = {
     "cqr_batched_instance": ([ctypes.c_int32, i32p, i32p, i32p, i32p], ctypes.c_int),
     "cqr_batched_plan_get": ([ctypes.c_int, i32p, i32p, i32p], ctypes.c_int),
     "cqr_batched_plan_set": ([ctypes.c_int, ctypes.c_int32, i32p, i32p], ctypes.c_int),
+    "cqr_svd_workspace_size": ([ctypes.c_int, i64, i64, i64, i64, szp], ctypes.c_int),
+    "cqr_lancsvd": ([i64, i64, vp, i64, i64, i64, ctypes.c_int, vp, i64, vp, i64, vp, vp, i64, vp, vp, ctypes.c_size_t,
+                     vp], ctypes.c_int),
+    "cqr_randsvd": ([i64, i64, vp, i64, i64, i64, ctypes.c_int, vp, i64, vp, i64, vp, vp, i64, vp, vp, ctypes.c_size_t,
+                     vp], ctypes.c_int),
+    "cqr_lancsvd_csr": ([i64, i64, i64, vp, vp, vp, vp, vp, vp, i64, i64, ctypes.c_int, vp, i64, vp, i64, vp, vp, i64,
+                         vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
+    "cqr_randsvd_csr": ([i64, i64, i64, vp, vp, vp, vp, vp, vp, i64, i64, ctypes.c_int, vp, i64, vp, i64, vp, vp, i64,
+                         vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
+    "cqr_small_svd_workspace_size": ([i64, szp], ctypes.c_int),
+    "cqr_small_svd": ([i64, vp, i64, vp, i64, vp, vp, i64, vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
+    "cqr_gemm_workspace_size": ([szp], ctypes.c_int),
+    "cqr_gemm": ([ctypes.c_int, i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, vp, ctypes.c_size_t, vp],
+                 ctypes.c_int),
+    "cqr_svd_residuals": ([i64, i64, vp, i64, i64, vp, i64, vp, vp, i64, vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
+    "cqr_spmm_workspace_size": ([i64, i64, szp], ctypes.c_int),
+    "cqr_spmm": ([ctypes.c_int, i64, i64, i64, vp, vp, vp, i64, vp, i64, vp, i64, vp, ctypes.c_size_t, vp],
+                 ctypes.c_int),
+    "cqr_csr_transpose_workspace_size": ([i64, szp], ctypes.c_int),
+    "cqr_csr_transpose": ([i64, i64, i64, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
     "cqr_prof_enable": ([ctypes.c_int], ctypes.c_int),
     "cqr_prof_reset": ([], ctypes.c_int),
     "cqr_prof_query": ([ctypes.c_char_p, i64p, dblp, dblp, dblp], ctypes.c_int),

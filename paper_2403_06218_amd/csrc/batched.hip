@@ -645,6 +645,77 @@ size_t batch_layout(int64_t count, char* base, int32_t** order, int32_t** range,
   return off;
 }
 
+// Enqueue the setup kernel and one persistent launch per bucket, with the
+// sort order, bucket ranges and work counters laid out at `work` (device
+// memory of at least batch_layout(count) bytes).  Arguments already checked.
+int batched_launch(int64_t count, int dtype, const int32_t* n, void* const* A, const int32_t* lda, void* const* R,
+                   const int32_t* ldr, void* const* B, int32_t* info, int32_t* flags, char* work, hipStream_t st) {
+  Plan plan;
+  {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    plan = g_plan[dtype];
+  }
+  SetupArgs sa;
+  memset(&sa, 0, sizeof(sa));
+  sa.count = (int)count;
+  sa.n = n;
+  sa.A = A;
+  sa.lda = lda;
+  sa.R = R;
+  sa.ldr = ldr;
+  sa.info = info;
+  sa.flags = flags;
+  batch_layout(count, work, &sa.order, &sa.range, &sa.counter);
+  sa.nbuckets = plan.nbuckets;
+  for (int b = 0; b < plan.nbuckets; ++b) sa.hi[b] = plan.hi[b];
+  int slot = prof_begin(st);
+  hipLaunchKernelGGL(batch_setup_kernel, dim3(1), dim3(1024), 0, st, sa);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return CQR_ERR_HIP_BASE - (int)e;
+  prof_end(slot, ROLE_BATCH_SETUP, st, 0.0, (double)count * 24);
+  // Largest sizes first: buckets from the top down.
+  for (int b = plan.nbuckets - 1; b >= 0; --b) {
+    const Instance& in = kInstances[plan.inst[b]];
+    const int grid = grid_for(in);
+    if (grid <= 0) return CQR_ERR_HIP_BASE - (int)hipErrorInvalidConfiguration;
+    BatchArgs ba;
+    ba.n = n;
+    ba.A = A;
+    ba.lda = lda;
+    ba.R = R;
+    ba.ldr = ldr;
+    ba.B = B;
+    ba.info = info;
+    ba.flags = flags;
+    ba.order = sa.order;
+    ba.range = sa.range;
+    ba.counter = sa.counter;
+    ba.bucket = b;
+    ba.bw = in.bw;
+    slot = prof_begin(st);
+    hipLaunchKernelGGL(in.fn, dim3(grid), dim3(in.waves * 64), 0, st, ba);
+    e = hipGetLastError();
+    if (e != hipSuccess) return CQR_ERR_HIP_BASE - (int)e;
+    prof_end(slot, ROLE_BATCH, st, 0.0, 0.0);
+  }
+  return CQR_OK;
+}
+
+// Argument checks shared by both entry points (the same return codes).
+int batched_check(int64_t count, int dtype, const int32_t* n, void* const* A, const int32_t* lda, void* const* R,
+                  const int32_t* ldr, const int32_t* info) {
+  if (count < 0 || count > INT32_MAX) return -1;
+  if (dtype != CQR_F64 && dtype != CQR_F32) return -2;
+  if (count == 0) return CQR_OK;
+  if (!n) return -3;
+  if (!A) return -4;
+  if (!lda) return -5;
+  if (!R) return -6;
+  if (!ldr) return -7;
+  if (!info) return -9;
+  return CQR_OK;
+}
+
 }  // namespace
 }  // namespace cqr
 
@@ -706,67 +777,11 @@ int cqr_batched_workspace_size(int64_t count, size_t* bytes) {
 int cqr_batched_factor_solve(int64_t count, int dtype, const int32_t* n, void* const* A, const int32_t* lda,
                              void* const* R, const int32_t* ldr, void* const* B, int32_t* info, int32_t* flags,
                              void* work, size_t work_bytes, void* stream) {
-  if (count < 0 || count > INT32_MAX) return -1;
-  if (dtype != CQR_F64 && dtype != CQR_F32) return -2;
-  if (count == 0) return CQR_OK;
-  if (!n) return -3;
-  if (!A) return -4;
-  if (!lda) return -5;
-  if (!R) return -6;
-  if (!ldr) return -7;
-  if (!info) return -9;
+  int rc = batched_check(count, dtype, n, A, lda, R, ldr, info);
+  if (rc != CQR_OK || count == 0) return rc;
   const size_t need = batch_layout(count, nullptr, nullptr, nullptr, nullptr);
   if (!work || work_bytes < need) return CQR_ERR_WORKSPACE;
-  hipStream_t st = (hipStream_t)stream;
-  Plan plan;
-  {
-    std::lock_guard<std::mutex> lk(g_plan_mu);
-    plan = g_plan[dtype];
-  }
-  SetupArgs sa;
-  memset(&sa, 0, sizeof(sa));
-  sa.count = (int)count;
-  sa.n = n;
-  sa.A = A;
-  sa.lda = lda;
-  sa.R = R;
-  sa.ldr = ldr;
-  sa.info = info;
-  sa.flags = flags;
-  batch_layout(count, (char*)work, &sa.order, &sa.range, &sa.counter);
-  sa.nbuckets = plan.nbuckets;
-  for (int b = 0; b < plan.nbuckets; ++b) sa.hi[b] = plan.hi[b];
-  int slot = prof_begin(st);
-  hipLaunchKernelGGL(batch_setup_kernel, dim3(1), dim3(1024), 0, st, sa);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return CQR_ERR_HIP_BASE - (int)e;
-  prof_end(slot, ROLE_BATCH_SETUP, st, 0.0, (double)count * 24);
-  // Largest sizes first: buckets from the top down.
-  for (int b = plan.nbuckets - 1; b >= 0; --b) {
-    const Instance& in = kInstances[plan.inst[b]];
-    const int grid = grid_for(in);
-    if (grid <= 0) return CQR_ERR_HIP_BASE - (int)hipErrorInvalidConfiguration;
-    BatchArgs ba;
-    ba.n = n;
-    ba.A = A;
-    ba.lda = lda;
-    ba.R = R;
-    ba.ldr = ldr;
-    ba.B = B;
-    ba.info = info;
-    ba.flags = flags;
-    ba.order = sa.order;
-    ba.range = sa.range;
-    ba.counter = sa.counter;
-    ba.bucket = b;
-    ba.bw = in.bw;
-    slot = prof_begin(st);
-    hipLaunchKernelGGL(in.fn, dim3(grid), dim3(in.waves * 64), 0, st, ba);
-    e = hipGetLastError();
-    if (e != hipSuccess) return CQR_ERR_HIP_BASE - (int)e;
-    prof_end(slot, ROLE_BATCH, st, 0.0, 0.0);
-  }
-  return CQR_OK;
+  return batched_launch(count, dtype, n, A, lda, R, ldr, B, info, flags, (char*)work, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -19,10 +19,17 @@
 //
 // Breakdown fallback (Section 3, CholeskyQR2 subsection): the Cholesky kernel
 // flags a pivot that is not > 0 in a status word; every later kernel of the
-// chain reads the word and exits, so a breakdown freezes the rest of the
-// factorisation.  At the end the host reads the word once; if it is set, the
-// failed block is restored from its saved copy and redone one column at a time
-// as Algorithm 5 with b = 1 (CGS2), then the blocked loop resumes.
+// block's chain reads the word and exits.  After each block one launch of the
+// CGS2 fallback kernel follows, gated on the same word: when it is set, that
+// launch restores the block from its saved copy, redoes it one column at a
+// time as Algorithm 5 with b = 1 (CGS2), records info and the block's flags in
+// device memory and clears the word, so the next block proceeds.  No step
+// reads anything back to the host: every call is stream-ordered and
+// asynchronous, and can be captured in a hipGraph.
+//
+// Blocks wider than 128 columns factor their Gram matrix as a 2 x 2 block
+// (two 128-wide Cholesky calls, the off-diagonal block and the Schur
+// complement by MFMA products).
 #include <mutex>
 #include <vector>
 #include <cstring>
@@ -57,10 +64,29 @@ hipEvent_t pool_get() {
 
 const char* const kRoleNames[ROLE_COUNT] = {"proj", "update", "gram", "trsm", "small", "reduce",
                                             "chol", "copy", "gemv", "trsv_inv", "trsv",
-                                            "batch", "batch_setup", "adjoint"};
+                                            "batch", "batch_setup", "adjoint", "fallback",
+                                            "aprod", "svd", "spmm"};
+
+// Bound of one bounded wait (grid barriers, look-back), microseconds.
+std::mutex g_wait_mu;
+int64_t g_wait_us = 10 * 1000 * 1000;
+int g_clock_khz = 0;
 }  // namespace
 
 const char* role_name(int role) { return (role >= 0 && role < ROLE_COUNT) ? kRoleNames[role] : nullptr; }
+
+uint64_t wait_limit_ticks() {
+  std::lock_guard<std::mutex> lk(g_wait_mu);
+  if (g_clock_khz <= 0) {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+      g_clock_khz = khz;
+    else
+      g_clock_khz = 100000;  // the documented 100 MHz of gfx9 devices
+  }
+  return (uint64_t)g_wait_us * (uint64_t)g_clock_khz / 1000u;
+}
 
 int prof_begin(hipStream_t s) {
   if (!g_prof_on) return -1;
@@ -86,7 +112,8 @@ void prof_end(int slot, int role, hipStream_t s, double flops, double bytes) {
 // ---------------------------------------------------------------- workspace
 namespace {
 
-constexpr int64_t kMaxB = 128;
+constexpr int64_t kMaxB = 256;
+constexpr int64_t kCholB = 128;  // widest Gram one Cholesky kernel factors; wider ones take the 2 x 2 split
 constexpr int64_t kMaxLd = 4000000;  // 32-bit in-tile offsets of the GEMM kernels
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -101,6 +128,8 @@ struct Work {
   double* T;     // q x b block after the first pass
   double* save;  // q x b copy of the block's input (fallback restore)
   double* Hb;    // (s) x b second-pass projection
+  double* ctmp;  // 128 x (b - 128) scratch of the 2 x 2 Cholesky (b > 128)
+  void* fb;      // fallback workspace (counters first)
   double* part;  // split-K partial sums
   size_t part_cap;
 };
@@ -137,6 +166,8 @@ size_t layout(int64_t q, int64_t r, int64_t b, char* base, Work* w) {
   o->T = (double*)take(qb);
   o->save = (double*)take(qb);
   o->Hb = (double*)take((size_t)(r > 0 ? r : 1) * (size_t)b * sizeof(double));
+  o->ctmp = (double*)take((size_t)kCholB * (size_t)(b > kCholB ? b - kCholB : 1) * sizeof(double));
+  o->fb = take(fallback_workspace_bytes(r > b ? r : b));
   o->part = (double*)take(cap * sizeof(double));
   o->part_cap = cap;
   return off;
@@ -158,9 +189,33 @@ struct Seg {
   int64_t ldh;
 };
 
-__global__ void set_status_kernel(int* status, int v0, int v1) {
-  status[0] = v0;
-  status[1] = v1;
+// Start of a call: clear the status word and the fallback counters, and
+// set info and the k block flags to 0 (device outputs; NULL skips them).
+__global__ void init_kernel(int* status, unsigned* fbctr, int32_t* info, int32_t* flags, int64_t k) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    status[0] = 0;
+    status[1] = 0;
+    fbctr[0] = 0u;
+    fbctr[1] = 0u;
+    fbctr[2] = 0u;
+    if (info) info[0] = 0;
+  }
+  if (flags && i < k) flags[i] = 0;
+}
+
+int init_call(const Work& ws, int32_t* info, int32_t* flags, int64_t k, hipStream_t st) {
+  const int64_t n = k > 1 ? k : 1;
+  hipLaunchKernelGGL(init_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ws.status, (unsigned*)ws.fb,
+                     info, flags, k);
+  CQR_TRY(hipGetLastError());
+  return CQR_OK;
+}
+
+// W = L L^T and (L^{-1})^T for a w x w Gram matrix (w <= 256).
+hipError_t chol_block(int w, double* W, double* LT, double* XT, const Work& ws, int code, int blk, hipStream_t st) {
+  if (w <= kCholB) return chol_inv(w, W, w, LT, XT, ws.status, code, blk, st);
+  return chol_inv_wide(w, W, w, LT, XT, ws.ctmp, ws.status, code, blk, st);
 }
 
 // Enqueue CGS-CQR2 (nseg >= 1) or CholeskyQR2 (nseg == 0) of the block Q
@@ -211,7 +266,7 @@ int orth_block(int64_t q, int64_t w, double* Q, int64_t ldq, const Seg* seg, int
                     st, 2.0 * dw * dq * (double)seg[i].s));
   CQR_TRY(gemm_tn(ROLE_GRAM, w, w, q, 1.0, Q, ldq, Q, ldq, 0.0, ws.W, w, ws.part, ws.part_cap, gate, st,
                   gram_flops));  // S3  W = Q^T Q
-  CQR_TRY(chol_inv((int)w, ws.W, w, ws.LT1, ws.XT1, ws.status, 1, blk, st));  // S4  W = L L^T
+  CQR_TRY(chol_block((int)w, ws.W, ws.LT1, ws.XT1, ws, 1, blk, st));  // S4  W = L L^T
   CQR_TRY(gemm_nn(ROLE_TRSM, q, w, w, 1.0, Q, ldq, ws.XT1, w, 0.0, ws.T, q, gate, st,
                   dw * dw * dq));  // S5  T = Q L^{-T}
   // ---- pass 2
@@ -229,7 +284,7 @@ int orth_block(int64_t q, int64_t w, double* Q, int64_t ldq, const Seg* seg, int
   }
   CQR_TRY(gemm_tn(ROLE_GRAM, w, w, q, 1.0, ws.T, q, ws.T, q, 0.0, ws.W, w, ws.part, ws.part_cap, gate, st,
                   gram_flops));  // S8  W = T^T T
-  CQR_TRY(chol_inv((int)w, ws.W, w, ws.LT2, ws.XT2, ws.status, 2, blk, st));  // S9  W = Lb Lb^T
+  CQR_TRY(chol_block((int)w, ws.W, ws.LT2, ws.XT2, ws, 2, blk, st));  // S9  W = Lb Lb^T
   CQR_TRY(gemm_nn(ROLE_TRSM, q, w, w, 1.0, ws.T, q, ws.XT2, w, 0.0, Q, ldq, gate, st,
                   dw * dw * dq));  // S10 Q = T Lb^{-T}
   // ---- combine
@@ -240,53 +295,6 @@ int orth_block(int64_t q, int64_t w, double* Q, int64_t ldq, const Seg* seg, int
     CQR_TRY(gemm_nn(ROLE_SMALL, seg[i].s, w, w, 1.0, ws.Hb + off, stot, ws.LT1, w, 1.0, seg[i].H, seg[i].ldh, gate,
                     st, dw * (double)seg[i].s));
     off += seg[i].s;
-  }
-  return CQR_OK;
-}
-
-int read_status(const Work& ws, hipStream_t st, int out[2]) {
-  CQR_TRY(hipStreamSynchronize(st));
-  CQR_TRY(hipMemcpy(out, ws.status, 2 * sizeof(int), hipMemcpyDeviceToHost));
-  return CQR_OK;
-}
-
-int reset_status(const Work& ws, hipStream_t st) {
-  hipLaunchKernelGGL(set_status_kernel, dim3(1), dim3(1), 0, st, ws.status, 0, 0);
-  CQR_TRY(hipGetLastError());
-  return CQR_OK;
-}
-
-// Fallback for the block of columns [c0, c0 + w) of Q: restore the input from
-// ws.save (when `restore`; the row-streaming form leaves it intact) and orthogonalise column by column (Algorithm 5 with b = 1) against
-// `pre` (up to one segment of earlier basis vectors) and the block's earlier
-// columns.  Hcol(c) gives where column c's projection on `pre` goes.
-// Returns CQR status; sets *zero if a column had no component left.
-int fallback_block(int64_t q, int64_t w, double* Qblk, int64_t ldq, const Seg* pre, double* Hpre, int64_t ldhpre,
-                   double* Rblk, int64_t ldr, const Work& ws, int blk, hipStream_t st, bool* zero, bool restore) {
-  int rc = reset_status(ws, st);
-  if (rc) return rc;
-  if (restore) CQR_TRY(copy_matrix(q, w, ws.save, q, Qblk, ldq, nullptr, st));
-  if (pre && pre->s > 0) CQR_TRY(zero_matrix(pre->s, w, Hpre, ldhpre, st));
-  CQR_TRY(zero_matrix(w, w, Rblk, ldr, st));
-  *zero = false;
-  for (int64_t c = 0; c < w; ++c) {
-    Seg segs[2];
-    int nseg = 0;
-    if (pre && pre->s > 0) segs[nseg++] = Seg{pre->P, pre->ldp, pre->s, Hpre + c * ldhpre, ldhpre};
-    if (c > 0) segs[nseg++] = Seg{Qblk, ldq, c, Rblk + c * ldr, ldr};
-    rc = orth_block(q, 1, Qblk + c * ldq, ldq, segs, nseg, Rblk + c + c * ldr, ldr, ws, blk, st, false);
-    if (rc) return rc;
-    int stv[2];
-    rc = read_status(ws, st, stv);
-    if (rc) return rc;
-    if (stv[0] != 0) {
-      // Nothing of the column is left outside the earlier ones: zero Q column, R_cc = 0.
-      CQR_TRY(zero_matrix(q, 1, Qblk + c * ldq, ldq, st));
-      CQR_TRY(zero_matrix(1, 1, Rblk + c + c * ldr, ldr, st));
-      *zero = true;
-      rc = reset_status(ws, st);
-      if (rc) return rc;
-    }
   }
   return CQR_OK;
 }
@@ -330,50 +338,30 @@ int cqr_factor(int64_t q, int64_t r, int64_t b, double* Y, int64_t ldy, double* 
   if (!R && r > 0) return -6;
   if (ldr < (r > 1 ? r : 1)) return -7;
   if (ldy > kMaxLd || ldr > kMaxLd) return CQR_ERR_UNSUPPORTED;
-  if (info) *info = 0;
   const int64_t k = (r + b - 1) / b;
-  if (block_flags)
-    for (int64_t i = 0; i < k; ++i) block_flags[i] = 0;
-  if (r == 0) return CQR_OK;
   const size_t need = layout(q, r, b, nullptr, nullptr);
   if (!work || work_bytes < need) return CQR_ERR_WORKSPACE;
   Work ws;
   layout(q, r, b, (char*)work, &ws);
   hipStream_t st = (hipStream_t)stream;
-
-  int rc = reset_status(ws, st);
+  int rc = init_call(ws, info, block_flags, k, st);
   if (rc) return rc;
+  if (r == 0) return CQR_OK;
   CQR_TRY(zero_matrix(r, r, R, ldr, st));
-  int64_t start = 0;
-  while (start < k) {
-    for (int64_t blk = start; blk < k; ++blk) {
-      const int64_t s = blk * b;
-      const int64_t w = (r - s < b) ? (r - s) : b;
-      double* Qj = Y + s * ldy;
-      // The row-streaming form leaves the block intact on a breakdown; the
-      // GEMM form works in place and keeps a copy for the fallback.
-      if (!tall_eligible(q, w, s)) CQR_TRY(copy_matrix(q, w, Qj, ldy, ws.save, q, ws.status, st));
-      Seg seg{Y, ldy, s, R + s * ldr, ldr};
-      rc = orth_block(q, w, Qj, ldy, &seg, s > 0 ? 1 : 0, R + s + s * ldr, ldr, ws, (int)blk, st);
-      if (rc) return rc;
-    }
-    int stv[2];
-    rc = read_status(ws, st, stv);
-    if (rc) return rc;
-    if (stv[0] == 0) break;
-    const int64_t blk = stv[1];
+  for (int64_t blk = 0; blk < k; ++blk) {
     const int64_t s = blk * b;
     const int64_t w = (r - s < b) ? (r - s) : b;
-    Seg pre{Y, ldy, s, nullptr, 0};
-    bool zero = false;
-    rc = fallback_block(q, w, Y + s * ldy, ldy, &pre, R + s * ldr, ldr, R + s + s * ldr, ldr, ws, (int)blk, st,
-                        &zero, !tall_eligible(q, w, s));
+    double* Qj = Y + s * ldy;
+    // The row-streaming form leaves the block intact on a breakdown; the
+    // GEMM form works in place and keeps a copy for the fallback.
+    const bool keep = !tall_eligible(q, w, s);
+    if (keep) CQR_TRY(copy_matrix(q, w, Qj, ldy, ws.save, q, ws.status, st));
+    Seg seg{Y, ldy, s, R + s * ldr, ldr};
+    rc = orth_block(q, w, Qj, ldy, &seg, s > 0 ? 1 : 0, R + s + s * ldr, ldr, ws, (int)blk, st);
     if (rc) return rc;
-    if (block_flags) block_flags[blk] |= CQR_FLAG_FALLBACK | (zero ? CQR_FLAG_ZERO_COL : 0);
-    if (info && *info == 0) *info = (int32_t)(blk + 1);
-    start = blk + 1;
+    CQR_TRY(cgs2_fallback(q, s, w, Y, ldy, Qj, ldy, R + s * ldr, ldr, R + s + s * ldr, ldr, keep ? ws.save : nullptr,
+                          ws.status, info, block_flags, (int)blk, ws.fb, st));
   }
-  CQR_TRY(hipStreamSynchronize(st));
   return CQR_OK;
 }
 
@@ -382,8 +370,7 @@ int cqr_orth(int64_t q, int64_t b, double* Q, int64_t ldq, double* R, int64_t ld
   if (q < 0) return -1;
   if (b < 1 || b > q) return -2;
   if (b > kMaxB) return CQR_ERR_UNSUPPORTED;
-  int32_t flags = 0;
-  return cqr_factor(q, b, b, Q, ldq, R, ldr, work, work_bytes, info, &flags, stream);
+  return cqr_factor(q, b, b, Q, ldq, R, ldr, work, work_bytes, info, nullptr, stream);
 }
 
 int cqr_orth_against(int64_t q, int64_t b, int64_t s, double* Q, int64_t ldq, const double* P, int64_t ldp,
@@ -402,29 +389,28 @@ int cqr_orth_against(int64_t q, int64_t b, int64_t s, double* Q, int64_t ldq, co
   if (!R) return -10;
   if (ldr < b) return -11;
   if (ldq > kMaxLd || ldp > kMaxLd || ldh > kMaxLd || ldr > kMaxLd) return CQR_ERR_UNSUPPORTED;
-  if (info) *info = 0;
   const size_t need = layout(q, s + b, b, nullptr, nullptr);
   if (!work || work_bytes < need) return CQR_ERR_WORKSPACE;
   Work ws;
   layout(q, s + b, b, (char*)work, &ws);
   hipStream_t st = (hipStream_t)stream;
-  int rc = reset_status(ws, st);
+  int rc = init_call(ws, info, nullptr, 0, st);
   if (rc) return rc;
   CQR_TRY(zero_matrix(b, b, R, ldr, st));
-  CQR_TRY(copy_matrix(q, b, Q, ldq, ws.save, q, nullptr, st));
+  const bool keep = !tall_eligible(q, b, s);
+  if (keep) CQR_TRY(copy_matrix(q, b, Q, ldq, ws.save, q, nullptr, st));
   Seg seg{P, ldp, s, H, ldh};
   rc = orth_block(q, b, Q, ldq, &seg, s > 0 ? 1 : 0, R, ldr, ws, 0, st);
   if (rc) return rc;
-  int stv[2];
-  rc = read_status(ws, st, stv);
-  if (rc) return rc;
-  if (stv[0] != 0) {
-    bool zero = false;
-    rc = fallback_block(q, b, Q, ldq, &seg, H, ldh, R, ldr, ws, 0, st, &zero, true);
-    if (rc) return rc;
-    if (info) *info = 1;
-  }
-  CQR_TRY(hipStreamSynchronize(st));
+  CQR_TRY(cgs2_fallback(q, s, b, P, ldp, Q, ldq, H, ldh, R, ldr, keep ? ws.save : nullptr, ws.status, info, nullptr, 0,
+                        ws.fb, st));
+  return CQR_OK;
+}
+
+int cqr_set_wait_limit_us(int64_t us) {
+  if (us < 0) return -1;
+  std::lock_guard<std::mutex> lk(g_wait_mu);
+  g_wait_us = us;
   return CQR_OK;
 }
 
@@ -436,7 +422,7 @@ int cqr_solve_workspace_size(int64_t n, size_t* bytes) {
 }
 
 int cqr_solve(int64_t n, const double* Q, int64_t ldq, const double* R, int64_t ldr, double* x, void* work,
-              size_t work_bytes, void* stream) {
+              size_t work_bytes, int32_t* status, void* stream) {
   if (n < 0) return -1;
   if (!Q && n > 0) return -2;
   if (ldq < (n > 1 ? n : 1)) return -3;
@@ -454,6 +440,7 @@ int cqr_solve(int64_t n, const double* Q, int64_t ldq, const double* R, int64_t 
   CQR_TRY(trsv_prepare(n, false, R, ldr, tw, st));
   CQR_TRY(trsv_solve(n, false, R, ldr, tw, y, 0, st));
   CQR_TRY(copy_matrix(n, 1, y, n, x, n, nullptr, st));
+  if (status) CQR_TRY(trsv_status(n, tw, status, st));
   return CQR_OK;
 }
 

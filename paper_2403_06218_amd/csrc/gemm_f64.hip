@@ -489,7 +489,7 @@ void pick_tile(bool ta, int64_t M, int64_t N, int nsplit, int* mt, int* nt, bool
 }
 
 Plan plan_gemm(bool ta, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda, const double* B, int64_t ldb,
-               bool allow_split, size_t part_cap, bool sym = false, bool tri = false) {
+               bool allow_split, size_t part_cap, bool sym = false, bool tri = false, bool skinny_ta = false) {
   Plan p;
   p.dma = dma_eligible(ta, M, K, A, lda, B, ldb);
   const int kt = p.dma ? kDmaKT : kKT;
@@ -500,10 +500,13 @@ Plan plan_gemm(bool ta, int64_t M, int64_t N, int64_t K, const double* A, int64_
   // about 2048 workgroups.  Small products that cannot split their reduction
   // (at most 256 x 256: the block Cholesky composition, R_jj = Lb^T L^T) take
   // 32 x 32 tiles, so that 16-64 workgroups share the work instead of 1-4.
+  // The truncated SVD's products A^T X with a block of at most 16 columns
+  // (skinny_ta) take a 128 x 16 tile, so that every element of A is read once
+  // and no MFMA work is spent on padding columns.
   if (p.dma) {
     if (ta && N <= 16 && M <= 64) { p.mt = 16; p.nt = 16; }
     else if (ta && M <= 32 && N <= 32) { p.mt = 32; p.nt = 32; }
-    else if (!ta && N <= 16 && M > 64) { p.mt = 128; p.nt = 16; }
+    else if ((!ta || skinny_ta) && N <= 16 && M > 64) { p.mt = 128; p.nt = 16; }
     else if (!(allow_split && ta) && M <= 256 && N <= 256) { p.mt = 32; p.nt = 32; }
   }
   if (p.mt != 0) {
@@ -600,10 +603,8 @@ hipError_t launch(const Plan& p, int64_t M, int64_t N, int64_t K, double alpha, 
     }
     if (p.mt == 32)
       return launch_dma<ROLE, TA, 32, 32, 3, 4>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
-    if (p.nt == 16) {
-      if constexpr (!TA)
-        return launch_dma<ROLE, TA, 128, 16, 3, 4, 2, 1>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
-    }
+    if (p.nt == 16 && p.mt == 128)
+      return launch_dma<ROLE, TA, 128, 16, 3, 4, 2, 1>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
     if (p.mt == 128 && p.nt == 128) {
       if (TA)
         return launch_dma<ROLE, TA, 128, 128, 2, 2, 4, 2>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
@@ -626,7 +627,8 @@ hipError_t gemm_tn(Role role, int64_t M, int64_t N, int64_t K, double alpha, con
                    const int* gate, hipStream_t s, double flops) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (!ld_ok(lda) || !ld_ok(ldb)) return hipErrorInvalidValue;
-  const Plan p = plan_gemm(true, M, N, K, A, lda, B, ldb, part != nullptr, part_cap, role == ROLE_GRAM && M == N);
+  const Plan p = plan_gemm(true, M, N, K, A, lda, B, ldb, part != nullptr, part_cap, role == ROLE_GRAM && M == N,
+                           false, role == ROLE_APROD);
   const double bytes = 8.0 * ((double)K * M + (double)K * N + (double)M * N * (beta != 0.0 ? 2.0 : 1.0));
   double* pp = p.nsplit > 1 ? part : nullptr;
   const int slot = prof_begin(s);
@@ -635,6 +637,8 @@ hipError_t gemm_tn(Role role, int64_t M, int64_t N, int64_t K, double alpha, con
     e = launch<ROLE_GRAM, true>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, pp, gate, s);
   else if (role == ROLE_CHOL)
     e = launch<ROLE_CHOL, true>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, pp, gate, s);
+  else if (role == ROLE_APROD)
+    e = launch<ROLE_APROD, true>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, pp, gate, s);
   else
     e = launch<ROLE_PROJ, true>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, pp, gate, s);
   prof_end(slot, role, s, flops, bytes);
@@ -668,6 +672,12 @@ hipError_t gemm_nn(Role role, int64_t M, int64_t N, int64_t K, double alpha, con
       break;
     case ROLE_CHOL:
       e = launch<ROLE_CHOL, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, gate, s);
+      break;
+    case ROLE_APROD:
+      e = launch<ROLE_APROD, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, gate, s);
+      break;
+    case ROLE_SVD:
+      e = launch<ROLE_SVD, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, gate, s);
       break;
     default:
       e = launch<ROLE_SMALL, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, gate, s);

@@ -26,6 +26,10 @@ enum Role : int {
   ROLE_BATCH,       // batched form: whole factorisation + solve, one workgroup per matrix
   ROLE_BATCH_SETUP, // batched form: size sort and bucket boundaries
   ROLE_ADJOINT,     // adjoint of the solve
+  ROLE_FALLBACK,    // breakdown fallback: the failed block redone by CGS2 (gated, one launch per block)
+  ROLE_APROD,       // truncated SVD: products with the input matrix, A X (NN) and A^T X (TN)
+  ROLE_SVD,         // truncated SVD: small dense SVD (one-sided Jacobi), B_k assembly, residuals
+  ROLE_SPMM,        // truncated SVD: sparse products A X and A^T X (CSR)
   ROLE_COUNT
 };
 
@@ -104,6 +108,42 @@ hipError_t copy_matrix(int64_t rows, int64_t cols, const double* src, int64_t ld
 // X (rows x cols) = 0.
 hipError_t zero_matrix(int64_t rows, int64_t cols, double* X, int64_t ldx, hipStream_t s);
 
+// Breakdown fallback (Section 3): redo the block Q (q x w, ldq) column by
+// column by CGS2 against P (q x s, ldp) and its own earlier columns, in one
+// launch gated on status[0] != 0 (an empty launch otherwise).  Restores the
+// block from `save` (q x w, ld q) first when save != NULL.  Writes H (s x w,
+// ldh) and R (w x w, ldr); sets flags[blk] and info (first block, 1-based) when
+// those are not NULL, then clears status.  `fbwork` holds
+// fallback_workspace_bytes(s + w) bytes whose first 256 bytes (the counters)
+// are zero before the first call; the kernel leaves them zero.
+size_t fallback_workspace_bytes(int64_t sw);
+hipError_t cgs2_fallback(int64_t q, int64_t s, int64_t w, const double* P, int64_t ldp, double* Q, int64_t ldq,
+                         double* H, int64_t ldh, double* R, int64_t ldr, const double* save, int* status,
+                         int32_t* info, int32_t* flags, int blk, void* fbwork, hipStream_t st);
+
+// Sparse matrix in CSR form with its transpose (also CSR), for the products
+// A X and A^T X of the truncated SVD.  Row pointers and column indices are
+// int32 (nnz < 2^31).  xrm: scratch of max(m, n) * 64 doubles holding the
+// dense operand in row-major order.
+struct SparseCsr {
+  int64_t m, n, nnz;
+  const int32_t* rowptr;   // m + 1
+  const int32_t* col;      // nnz
+  const double* val;       // nnz
+  const int32_t* trowptr;  // n + 1 (CSR of A^T)
+  const int32_t* tcol;
+  const double* tval;
+  double* xrm;
+};
+// C (m x w, ldc) = A X (X n x w, ldx), or with trans C (n x w) = A^T X (X m x w).
+hipError_t spmm(const SparseCsr& S, bool trans, int64_t w, const double* X, int64_t ldx, double* C, int64_t ldc,
+                hipStream_t st);
+size_t spmm_scratch_doubles(int64_t m, int64_t n);
+
+// Bound of one wait of a bounded wait loop (grid barrier, look-back), in
+// ticks of the device's constant-rate clock (wall_clock64).
+uint64_t wait_limit_ticks();
+
 // Solve kernels.
 hipError_t gemv_t(int64_t n, const double* Q, int64_t ldq, const double* x, double* y, hipStream_t s);
 
@@ -112,11 +152,13 @@ hipError_t gemv_t(int64_t n, const double* Q, int64_t ldq, const double* x, doub
 // 64 x 64 diagonal blocks in `work` (trsv_workspace_bytes(n)) and clears its
 // counters; then trsv_solve calls number seq = 0, 1, 2, ... of that sequence
 // each solve one right-hand side with the same R.  *trsv_error_word(n, work)
-// is nonzero if a wait was abandoned (the result is then not valid).
+// is nonzero if a wait was abandoned (the x block published after it is NaN).
+// trsv_status copies that word into status[0] (device, int32: 0 or 1).
 size_t trsv_workspace_bytes(int64_t n);
 hipError_t trsv_prepare(int64_t n, bool f32, const void* R, int64_t ldr, void* work, hipStream_t s);
 hipError_t trsv_solve(int64_t n, bool f32, const void* R, int64_t ldr, void* work, double* y, int64_t seq,
                       hipStream_t s);
 const unsigned* trsv_error_word(int64_t n, const void* work);
+hipError_t trsv_status(int64_t n, const void* work, int32_t* status, hipStream_t s);
 
 }  // namespace cqr

@@ -20,9 +20,10 @@
 // relaxed polling plus an acquire fence by the waiting ones, agent scope, so
 // the x values cross XCDs through memory).  Both counters only grow: launch
 // number k of a sequence passes base = k * nblk, and the inverse launch
-// clears them at the start of a sequence.  Every wait is bounded: past the
-// spin limit the workgroup sets an error word, carries on with whatever it
-// has and still publishes, so every workgroup exits.
+// clears them at the start of a sequence.  Every wait is bounded (in time, on
+// the device's constant-rate clock): past the bound the workgroup sets an
+// error word, carries on and publishes NaN for its block (so that every block
+// that depends on it is NaN too), so every workgroup exits.
 #include "internal.h"
 #include "wave_chol.h"
 
@@ -31,7 +32,6 @@ namespace {
 
 constexpr int kTB = 64;                   // rows per block
 constexpr int kTThreads = 256;            // lookback workgroup: 4 waves x 16 columns of each block
-constexpr unsigned kSpinLimit = 1u << 22; // polls before a wait is abandoned (seconds)
 
 template <typename TR>
 __global__ void __launch_bounds__(kTB)
@@ -73,14 +73,18 @@ trsv_inv_kernel(int64_t n, const TR* __restrict__ R, int64_t ldr, double* __rest
 template <typename TR>
 __global__ void __launch_bounds__(kTThreads)
 trsv_lookback_kernel(int64_t n, const TR* __restrict__ R, int64_t ldr, const double* __restrict__ Dinv,
-                     double* y, unsigned* ctr, unsigned base) {
+                     double* y, unsigned* ctr, unsigned base, uint64_t wait_ticks) {
   __shared__ unsigned sTicket;
+  __shared__ int sGaveUp;
   __shared__ double sPart[kTThreads / 64][kTB];
   __shared__ double sV[kTB];
   __shared__ unsigned sDone[2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const unsigned nblk = (unsigned)((n + kTB - 1) / kTB);
-  if (tid == 0) sTicket = atomicAdd(&ctr[0], 1u);
+  if (tid == 0) {
+    sTicket = atomicAdd(&ctr[0], 1u);
+    sGaveUp = 0;
+  }
   __syncthreads();
   const unsigned tk = sTicket - base;
   // Tickets past this launch's range cannot occur while launches of one
@@ -115,7 +119,7 @@ trsv_lookback_kernel(int64_t n, const TR* __restrict__ R, int64_t ldr, const dou
   // the count it saw to the other waves through LDS behind a barrier; the
   // slot alternates so that a fast wave 0 never overwrites a count that a
   // slower wave has yet to read.
-  unsigned spins = 0;
+  const uint64_t t0 = wall_clock64();
   int par = 0;
   while (next > I) {
     // Block `next` is finished once done - base >= nblk - next.
@@ -123,14 +127,21 @@ trsv_lookback_kernel(int64_t n, const TR* __restrict__ R, int64_t ldr, const dou
     if (wave == 0) {
       unsigned d = __builtin_amdgcn_readfirstlane(
           __hip_atomic_load(&ctr[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - base);
-      while (d < want && spins < kSpinLimit) {
+      bool late = false;
+      while (d < want) {
+        if (wall_clock64() - t0 > wait_ticks) {
+          late = true;
+          break;
+        }
         __builtin_amdgcn_s_sleep(2);
-        ++spins;
         d = __builtin_amdgcn_readfirstlane(
             __hip_atomic_load(&ctr[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - base);
       }
-      if (d < want) {
-        if (lane == 0) __hip_atomic_store(&ctr[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (late) {
+        if (lane == 0) {
+          __hip_atomic_store(&ctr[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          sGaveUp = 1;
+        }
         d = want;
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -165,7 +176,8 @@ trsv_lookback_kernel(int64_t n, const TR* __restrict__ R, int64_t ldr, const dou
   for (int c = 0; c < 16; ++c) px += dv[c] * sV[16 * wave + c];
   sPart[wave][lane] = px;
   __syncthreads();
-  if (wave == 0 && rowok) y[row] = (sPart[0][lane] + sPart[1][lane]) + (sPart[2][lane] + sPart[3][lane]);
+  if (wave == 0 && rowok)
+    y[row] = sGaveUp ? __builtin_nan("") : (sPart[0][lane] + sPart[1][lane]) + (sPart[2][lane] + sPart[3][lane]);
   __syncthreads();
   if (tid == 0) __hip_atomic_store(&ctr[1], base + nblk - (unsigned)I, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -208,10 +220,10 @@ hipError_t trsv_solve(int64_t n, bool f32, const void* R, int64_t ldr, void* wor
   const int slot = prof_begin(s);
   if (f32)
     hipLaunchKernelGGL(trsv_lookback_kernel<float>, dim3((unsigned)nblk), dim3(kTThreads), 0, s, n, (const float*)R,
-                       ldr, Dinv, y, ctr, base);
+                       ldr, Dinv, y, ctr, base, wait_limit_ticks());
   else
     hipLaunchKernelGGL(trsv_lookback_kernel<double>, dim3((unsigned)nblk), dim3(kTThreads), 0, s, n,
-                       (const double*)R, ldr, Dinv, y, ctr, base);
+                       (const double*)R, ldr, Dinv, y, ctr, base, wait_limit_ticks());
   const hipError_t e = hipGetLastError();
   const double dn = (double)n;
   prof_end(slot, ROLE_TRSV, s, dn * dn, (f32 ? 4.0 : 8.0) * dn * dn / 2.0 + 8.0 * dn * kTB + 16.0 * dn);
@@ -220,6 +232,15 @@ hipError_t trsv_solve(int64_t n, bool f32, const void* R, int64_t ldr, void* wor
 
 const unsigned* trsv_error_word(int64_t n, const void* work) {
   return (const unsigned*)((const char*)work + trsv_workspace_bytes(n) - 256) + 2;
+}
+
+namespace {
+__global__ void trsv_status_kernel(const unsigned* err, int32_t* status) { status[0] = err[0] != 0u ? 1 : 0; }
+}  // namespace
+
+hipError_t trsv_status(int64_t n, const void* work, int32_t* status, hipStream_t s) {
+  hipLaunchKernelGGL(trsv_status_kernel, dim3(1), dim3(1), 0, s, trsv_error_word(n, work), status);
+  return hipGetLastError();
 }
 
 }  // namespace cqr

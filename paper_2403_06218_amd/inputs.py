@@ -144,25 +144,100 @@ def svd_test_sigma(n: int) -> np.ndarray:
     return np.concatenate([top[::-1], np.full(n - h, 1e-14)])
 
 
-def svd_test_matrix(m: int, n: int, seed: int):
-    """A = X Sigma Y^T (m x n, column-major) with the singular values of
-    ``svd_test_sigma`` and random orthogonal factors.  Y is the Q factor of an
-    n x n Gaussian matrix; X (m x n, m a multiple c of n) stacks c row blocks
-    D_l Z P_l / sqrt(c), with Z the Q factor of another n x n Gaussian matrix,
-    D_l random signs and P_l random column permutations, so that
-    X^T X = I exactly in exact arithmetic and large m stays cheap.  Returns
-    (A, sigma)."""
+def _unit_normals(count: int, n: int, seed: int) -> list:
+    """``count`` unit vectors of length n with N(0, 1) directions (counter stream)."""
+    out = []
+    for c in range(count):
+        t = np.arange(n, dtype=np.uint64) + np.uint64(c * n)
+        u1 = uniform01(seed, t)
+        u2 = uniform01(seed ^ 0x5DEECE66D, t)
+        v = np.sqrt(-2.0 * np.log1p(-u1)) * np.cos(2.0 * np.pi * u2)
+        out.append(v / np.linalg.norm(v))
+    return out
+
+
+def svd_test_parts(m: int, n: int, seed: int) -> dict:
+    """The random ingredients of ``svd_test_matrix``: unit vectors of four
+    Householder reflectors for each of the orthogonal factors Z and Y, and per
+    row block l of X a sign vector and a column permutation."""
     if m % n:
         raise ValueError("m must be a multiple of n")
     c = m // n
-    rng = np.random.default_rng(seed)
-    Y, _ = np.linalg.qr(rng.standard_normal((n, n)))
-    Z, _ = np.linalg.qr(rng.standard_normal((n, n)))
-    sig = svd_test_sigma(n)
-    SYt = sig[:, None] * Y.T
+    zs = _unit_normals(4, n, seed + 1)
+    ys = _unit_normals(4, n, seed + 2)
+    signs, perms = [], []
+    for l in range(c):
+        t = np.arange(n, dtype=np.uint64)
+        signs.append(np.where(uniform01(seed + 3 + 2 * l, t) < 0.5, -1.0, 1.0))
+        perms.append(np.argsort(uniform01(seed + 4 + 2 * l, t), kind="stable"))
+    return {"c": c, "zs": zs, "ys": ys, "signs": signs, "perms": perms, "sigma": svd_test_sigma(n)}
+
+
+def svd_test_matrix(m: int, n: int, seed: int):
+    """A = X Sigma Y^T (m x n, column-major) with the singular values of
+    ``svd_test_sigma``.  Y = H(y1) H(y2) H(y3) H(y4) is a product of four random
+    Householder reflectors H(v) = I - 2 v v^T (dense and orthogonal); X (m x n,
+    m a multiple c of n) stacks c row blocks D_l Z P_l / sqrt(c) with Z another
+    such product, D_l random signs and P_l random column permutations, so that
+    X^T X = I in exact arithmetic and large m stays cheap (block l of A is
+    D_l (Z P_l Sigma) Y^T / sqrt(c); the reflectors are applied, never
+    factorised).  Returns (A, sigma)."""
+    parts = svd_test_parts(m, n, seed)
+    c, sig = parts["c"], parts["sigma"]
+    Z = np.eye(n)
+    for z in parts["zs"]:
+        Z -= 2.0 * np.outer(Z @ z, z)
     A = np.empty((m, n), order="F")
     for l in range(c):
-        d = rng.choice(np.array([-1.0, 1.0]), size=n)
-        perm = rng.permutation(n)
-        A[l * n:(l + 1) * n, :] = (d[:, None] * Z[:, perm]) @ SYt / np.sqrt(c)
+        M = Z[:, parts["perms"][l]] * sig
+        for y in reversed(parts["ys"]):
+            M -= 2.0 * np.outer(M @ y, y)
+        A[l * n:(l + 1) * n, :] = parts["signs"][l][:, None] * M / np.sqrt(c)
     return A, sig
+
+
+def svd_test_matrix_device(m: int, n: int, seed: int, device="cuda"):
+    """``svd_test_matrix`` built on the GPU with torch from the same random
+    ingredients (the same matrix up to rounding), column-major (m, n) with
+    leading dimension m; for sizes the host cannot hold (m = 1e6, n = 1e4 is
+    80 GB)."""
+    import torch
+    parts = svd_test_parts(m, n, seed)
+    c = parts["c"]
+    sig = torch.from_numpy(parts["sigma"]).to(device)
+    Z = torch.eye(n, dtype=torch.float64, device=device)
+    for z in parts["zs"]:
+        zt = torch.from_numpy(z).to(device)
+        Z.sub_(2.0 * torch.outer(Z @ zt, zt))
+    ys = [torch.from_numpy(y).to(device) for y in reversed(parts["ys"])]
+    A = torch.empty((n, m), dtype=torch.float64, device=device).t()
+    for l in range(c):
+        M = Z.index_select(1, torch.from_numpy(parts["perms"][l]).to(device)) * sig
+        for yt in ys:
+            M.sub_(2.0 * torch.outer(M @ yt, yt))
+        d = torch.from_numpy(parts["signs"][l]).to(device)
+        A[l * n:(l + 1) * n, :] = d[:, None] * M / float(np.sqrt(c))
+        del M
+    return A, parts["sigma"]
+
+
+def sparse_matrix(m: int, n: int, nnz: int, seed: int):
+    """Synthetic sparse m x n matrix in CSR form (int32 row pointers and
+    sorted column indices, float64 values U[-1, 1)) with about ``nnz``
+    nonzeros: heavy-tailed row lengths (length_i proportional to
+    (1 - u_i)^(-1/2), at least 1, at most n, rescaled to the requested total)
+    and uniformly drawn columns, duplicates within a row dropped.  Returns
+    (rowptr, col, val)."""
+    u = uniform01(seed, np.arange(m, dtype=np.uint64))
+    w = (1.0 - u) ** -0.5
+    lens = np.maximum(1, np.minimum(n, np.round(w * (nnz / w.sum())))).astype(np.int64)
+    total = int(lens.sum())
+    rows = np.repeat(np.arange(m, dtype=np.int64), lens)
+    cols = np.floor(uniform01(seed + 1, np.arange(total, dtype=np.uint64)) * n).astype(np.int64)
+    key = np.unique(rows * n + cols)
+    rows, cols = key // n, key % n
+    rowptr = np.zeros(m + 1, dtype=np.int64)
+    np.add.at(rowptr, rows + 1, 1)
+    rowptr = np.cumsum(rowptr)
+    vals = _affine(uniform01(seed + 2, np.arange(key.size, dtype=np.uint64)), -1.0, 1.0)
+    return rowptr.astype(np.int32), cols.astype(np.int32), vals

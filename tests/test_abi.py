@@ -36,26 +36,26 @@ def test_argument_validation_returns_lapack_style_codes():
     assert lib.cqr_workspace_size(-1, 0, 1, ctypes.byref(nb)) == -1
     assert lib.cqr_workspace_size(4, 5, 1, ctypes.byref(nb)) == -2
     assert lib.cqr_workspace_size(4, 4, 0, ctypes.byref(nb)) == -3
-    assert lib.cqr_workspace_size(400, 400, 129, ctypes.byref(nb)) == -100
+    assert lib.cqr_workspace_size(400, 400, 257, ctypes.byref(nb)) == -100
     assert lib.cqr_workspace_size(1000, 500, 64, ctypes.byref(nb)) == 0 and nb.value > 1000 * 64 * 8
-    flags = (ctypes.c_int32 * 4)()
-    info = ctypes.c_int32(0)
     v = ctypes.c_void_p(0x1000)  # never dereferenced: every case fails validation first
-    assert lib.cqr_factor(-1, 1, 1, v, 1, v, 1, v, 1 << 30, ctypes.byref(info), flags, None) == -1
-    assert lib.cqr_factor(3, 4, 1, v, 3, v, 4, v, 1 << 30, ctypes.byref(info), flags, None) == -2
-    assert lib.cqr_factor(4, 4, 0, v, 4, v, 4, v, 1 << 30, ctypes.byref(info), flags, None) == -3
-    assert lib.cqr_factor(4, 4, 2, None, 4, v, 4, v, 1 << 30, ctypes.byref(info), flags, None) == -4
-    assert lib.cqr_factor(4, 4, 2, v, 3, v, 4, v, 1 << 30, ctypes.byref(info), flags, None) == -5
-    assert lib.cqr_factor(4, 4, 2, v, 4, None, 4, v, 1 << 30, ctypes.byref(info), flags, None) == -6
-    assert lib.cqr_factor(4, 4, 2, v, 4, v, 3, v, 1 << 30, ctypes.byref(info), flags, None) == -7
-    assert lib.cqr_factor(4, 4, 2, v, 4, v, 4, None, 0, ctypes.byref(info), flags, None) == -101
-    assert lib.cqr_factor(4, 4, 2, v, 4, v, 4, v, 16, ctypes.byref(info), flags, None) == -101
-    assert lib.cqr_factor(4, 4, 200, v, 4, v, 4, v, 1 << 30, ctypes.byref(info), flags, None) == -100
-    assert lib.cqr_orth_against(10, 4, 7, v, 10, v, 10, v, 7, v, 4, v, 1 << 30, ctypes.byref(info), None) == -3
-    assert lib.cqr_orth_against(10, 4, 3, v, 10, v, 9, v, 3, v, 4, v, 1 << 30, ctypes.byref(info), None) == -7
-    assert lib.cqr_solve(-1, v, 1, v, 1, v, v, 8, None) == -1
-    assert lib.cqr_solve(4, v, 3, v, 4, v, v, 64, None) == -3
-    assert lib.cqr_solve(4, v, 4, v, 4, v, v, 8, None) == -101
+    info = flags = v
+    assert lib.cqr_factor(-1, 1, 1, v, 1, v, 1, v, 1 << 30, info, flags, None) == -1
+    assert lib.cqr_factor(3, 4, 1, v, 3, v, 4, v, 1 << 30, info, flags, None) == -2
+    assert lib.cqr_factor(4, 4, 0, v, 4, v, 4, v, 1 << 30, info, flags, None) == -3
+    assert lib.cqr_factor(4, 4, 2, None, 4, v, 4, v, 1 << 30, info, flags, None) == -4
+    assert lib.cqr_factor(4, 4, 2, v, 3, v, 4, v, 1 << 30, info, flags, None) == -5
+    assert lib.cqr_factor(4, 4, 2, v, 4, None, 4, v, 1 << 30, info, flags, None) == -6
+    assert lib.cqr_factor(4, 4, 2, v, 4, v, 3, v, 1 << 30, info, flags, None) == -7
+    assert lib.cqr_factor(4, 4, 2, v, 4, v, 4, None, 0, info, flags, None) == -101
+    assert lib.cqr_factor(4, 4, 2, v, 4, v, 4, v, 16, info, flags, None) == -101
+    assert lib.cqr_factor(4, 4, 300, v, 4, v, 4, v, 1 << 30, info, flags, None) == -100
+    assert lib.cqr_orth_against(10, 4, 7, v, 10, v, 10, v, 7, v, 4, v, 1 << 30, info, None) == -3
+    assert lib.cqr_orth_against(10, 4, 3, v, 10, v, 9, v, 3, v, 4, v, 1 << 30, info, None) == -7
+    assert lib.cqr_solve(-1, v, 1, v, 1, v, v, 8, v, None) == -1
+    assert lib.cqr_solve(4, v, 3, v, 4, v, v, 64, v, None) == -3
+    assert lib.cqr_solve(4, v, 4, v, 4, v, v, 8, v, None) == -101
+    assert lib.cqr_set_wait_limit_us(-1) == -1
     assert b"invalid argument" in lib.cqr_status_string(-3)
     assert b"workspace" in lib.cqr_status_string(-101)
     syn = _native.synth_lib()

@@ -1,0 +1,168 @@
+"""The asynchronous boundary of the FP64 path, through the C ABI: cqr_factor
+decides and runs the breakdown fallback (Section 3) on the device, writes info
+and the block flags to device memory and never synchronises, so the whole
+factorisation can be captured in a hipGraph; the bounded waits of the
+fallback's grid barriers and of the back substitution report an abandoned
+wait instead of hanging or returning a silently wrong result; block widths
+above 128 factor their Gram matrix as a 2 x 2 block.
+
+The abandoned-wait cases force the condition from the host by setting the
+wait bound to zero: every kernel still runs to its end (all accesses stay in
+bounds, every wait is bounded), only the reported status changes.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2403_06218_amd as cqr
+from paper_2403_06218_amd import inputs
+from gpu_util import EPS, orth_ratio, recon_ratio, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+INFO_WAIT_ABANDONED = -2
+DEFAULT_WAIT_US = 10 * 1000 * 1000
+
+
+def _hilbert_case(q, w, nblk, bad, seed):
+    Y = inputs.uniform_matrix(q, nblk * w, seed=seed)
+    i, j = np.arange(q), np.arange(w)
+    Y[:, bad * w:(bad + 1) * w] = 1.0 / (i[:, None] + j[None, :] + 1.0)
+    return Y
+
+
+def test_factor_is_asynchronous_and_reports_on_device():
+    """info and flags arrive in device tensors; the host learns them only by
+    reading those tensors (a Hilbert block forces the fallback in block 2)."""
+    Y = _hilbert_case(300, 16, 4, 1, seed=31)
+    Yd = to_dev(Y)
+    Q, R, info, flags = cqr.qr_async(Yd, 16)
+    assert info.is_cuda and flags.is_cuda
+    torch.cuda.synchronize()
+    ref = oracle.cgs_qr(Y, 16)
+    assert int(info[0]) == ref["info"] == 2
+    assert flags.cpu().tolist() == list(ref["block_flags"]) == [0, 1, 0, 0]
+    Qg, Rg = to_host(Q), to_host(R)
+    assert np.linalg.norm(Y - Qg @ Rg) < 1e-13 * np.linalg.norm(Y)
+    assert orth_ratio(Qg) < 16
+
+
+def test_factor_graph_replay_with_fallback_matches_eager():
+    """The whole factorisation, the fallback of a Hilbert block included,
+    captured in a hipGraph: every replay (eager calls in between) gives the
+    eager call's bits, info and flags."""
+    q, w = 2000, 32
+    Y = _hilbert_case(q, w, 5, 2, seed=32)
+    src = to_dev(Y)
+    Yw = cqr.colmajor(q, Y.shape[1])
+    R = cqr.colmajor(Y.shape[1], Y.shape[1])
+    work = torch.empty(cqr.workspace_size(q, Y.shape[1], w), dtype=torch.uint8, device="cuda")
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    flags = torch.zeros(5, dtype=torch.int32, device="cuda")
+    Yw.copy_(src)
+    cqr.qr_async(Yw, w, R=R, work=work, info=info, flags=flags)
+    torch.cuda.synchronize()
+    Qe, Re, ie, fe = Yw.clone(), R.clone(), info.clone(), flags.clone()
+    assert int(ie[0]) == 3 and fe.cpu().tolist() == [0, 0, 1, 0, 0]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        Yw.copy_(src)
+        cqr.qr_async(Yw, w, R=R, work=work, info=info, flags=flags)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        Yw.copy_(src)
+        cqr.qr_async(Yw, w, R=R, work=work, info=info, flags=flags)
+    for _ in range(3):
+        # eager work between replays, on other buffers
+        Z = to_dev(inputs.uniform_matrix(500, 64, seed=33))
+        cqr.qr(Z, 16)
+        Yw.fill_(float("nan"))
+        R.fill_(float("nan"))
+        info.fill_(-9)
+        flags.fill_(-9)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(Yw, Qe) and torch.equal(R, Re)
+        assert torch.equal(info, ie) and torch.equal(flags, fe)
+
+
+@pytest.mark.parametrize("q,r,b", [(1000, 600, 256), (700, 700, 200), (3000, 512, 256), (600, 300, 160)])
+def test_wide_blocks_match_oracle(q, r, b):
+    """Block widths 129..256: 2 x 2 block Cholesky of the Gram matrix."""
+    Y = inputs.uniform_matrix(q, r, seed=q + r + b)
+    Yd = to_dev(Y)
+    Q, R, info, flags = cqr.qr(Yd, b)
+    Qg, Rg = to_host(Q), to_host(R)
+    ref = oracle.cgs_qr(Y, b)
+    assert info == ref["info"] == 0 and list(flags) == list(ref["block_flags"])
+    tol = 8 * np.linalg.cond(Y) * q * EPS
+    np.testing.assert_allclose(Qg, ref["Q"], rtol=0, atol=tol)
+    np.testing.assert_allclose(Rg, ref["R"], rtol=0, atol=tol * np.linalg.norm(Y, 2))
+    assert recon_ratio(Y, Qg, Rg) < 16 and orth_ratio(Qg) < 16
+
+
+def test_wide_block_fallback():
+    """A Hilbert block of width 192 breaks one of the two Cholesky calls of the
+    2 x 2 split; the block falls back to CGS2 with the oracle's info/flags."""
+    Y = _hilbert_case(1500, 192, 3, 1, seed=34)
+    Yd = to_dev(Y)
+    Q, R, info, flags = cqr.qr(Yd, 192)
+    ref = oracle.cgs_qr(Y, 192)
+    assert info == ref["info"] == 2
+    assert list(flags) == list(ref["block_flags"])
+    Qg, Rg = to_host(Q), to_host(R)
+    assert np.linalg.norm(Y - Qg @ Rg) < 1e-13 * np.linalg.norm(Y)
+    assert orth_ratio(Qg) < 16
+
+
+def test_solve_reports_abandoned_wait():
+    """With the wait bound at zero the back substitution gives up on its
+    first wait: it still ends, reports status 1 and poisons x with NaN.  With
+    the default bound the same solve is exact again."""
+    n = 8192
+    Rh = np.triu(inputs.uniform_matrix(n, n, 35))
+    np.fill_diagonal(Rh, 1.0 + np.abs(Rh).sum(axis=1))
+    Rd = to_dev(Rh)
+    Qd = cqr.colmajor(n, n)
+    Qd.zero_()
+    Qd.diagonal().fill_(1.0)
+    c = torch.from_numpy(inputs.uniform_vector(n, 36)).cuda()
+    st = torch.full((1,), -9, dtype=torch.int32, device="cuda")
+    try:
+        cqr.set_wait_limit_us(0)
+        x = cqr.solve(Qd, Rd, c, status=st)
+        torch.cuda.synchronize()
+    finally:
+        cqr.set_wait_limit_us(DEFAULT_WAIT_US)
+    assert int(st[0]) == 1
+    assert torch.isnan(x).any()
+    x = cqr.solve(Qd, Rd, c, status=st)
+    torch.cuda.synchronize()
+    assert int(st[0]) == 0
+    assert not torch.isnan(x).any()
+
+
+def test_fallback_reports_abandoned_wait():
+    """The fallback's grid barriers with a zero wait bound: the launch still
+    ends and info reports the abandoned wait; the default bound restores the
+    oracle's info.  A zero first column makes the block's first pivot exactly
+    0, so the fallback is certain to run (on 256 workgroups at q = 65536)."""
+    Y = inputs.uniform_matrix(65536, 16, seed=37)
+    Y[:, 8] = 0.0
+    try:
+        cqr.set_wait_limit_us(0)
+        _, _, info, _ = cqr.qr(to_dev(Y), 8)
+    finally:
+        cqr.set_wait_limit_us(DEFAULT_WAIT_US)
+    assert info == INFO_WAIT_ABANDONED
+    _, _, info, flags = cqr.qr(to_dev(Y), 8)
+    ref = oracle.cgs_qr(Y, 8)
+    assert info == ref["info"] == 2 and flags == list(ref["block_flags"]) == [0, 3]

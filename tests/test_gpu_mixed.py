@@ -31,7 +31,7 @@ def _host32(T):
 
 
 @pytest.mark.parametrize("n,b", [(512, 64), (512, 128), (1000, 64), (2048, 128), (1024, 256), (1000, 256),
-                                 (700, 256), (600, 144)])
+                                 (700, 256), (600, 144), (4096, 256)])
 def test_mixed_factor_against_oracle(n, b):
     """Diagonally dominant input (off-diagonal U[-0.5, 0.5], diagonal = row sum + 1)."""
     Y = inputs.diag_dominant(n, seed=n)
@@ -113,6 +113,30 @@ def test_fp8_factor_backward_error(n, b):
     orth = np.abs(Qh.T @ Qh - np.eye(n)).max()
     assert rec < 2 * U_FP8, rec
     assert orth < 4 * U_FP8, orth
+
+
+@pytest.mark.parametrize("n,b", [(2048, 256), (1024, 64)])
+def test_fp8_factor_against_oracle(n, b):
+    """FP8 factors element by element against the oracle's FP64 factors.
+    With E = Y - Q R and F = I - Q^T Q measured on the FP8 result, first-order
+    QR perturbation theory (exact orthonormal factors of Y + E) bounds
+    ||dQ||_F by sqrt(2) kappa_2(Y) ||E||_F / ||Y||_2, and the departure of Q
+    from orthonormality adds at most ||F||_F; twice that sum allows for the
+    second-order terms.  R is bounded the same way relative to ||Y||_2."""
+    Y = inputs.diag_dominant(n, seed=n + 5)
+    Q, R, info = cqr.qr_mixed(to_dev(Y), b, prec=cqr.PREC_FP8)
+    torch.cuda.synchronize()
+    assert info == 0
+    Qh, Rh = _host32(Q), _host32(R)
+    ref = oracle.cgs_qr(Y, b)
+    n2 = np.linalg.norm(Y, 2)
+    kappa = np.linalg.cond(Y)
+    e = np.linalg.norm(Y - Qh @ Rh) / n2
+    f = np.linalg.norm(Qh.T @ Qh - np.eye(n))
+    assert e < 2 * U_FP8 and np.abs(Qh.T @ Qh - np.eye(n)).max() < 4 * U_FP8
+    bound = 2 * (np.sqrt(2) * kappa * e + f)
+    assert np.abs(Qh - ref["Q"]).max() < bound
+    assert np.abs(Rh - ref["R"]).max() < bound * n2
 
 
 @pytest.mark.parametrize("n,b", [(512, 64), (4096, 256)])

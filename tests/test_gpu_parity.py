@@ -83,6 +83,39 @@ def test_ragged_and_edge_shapes(q, r, b):
     _compare(Y, b, Qg, Rg, info, flags)
 
 
+def test_full_size_update_tile_q32768():
+    """q = 32768 rows at b = 128: the update Q -= PH runs on the 128 x 128
+    tile (ceil(q/128) * ceil(b/128) = 256 workgroups, the instance the
+    n = 32768 square workload uses for every block), the projection and Gram
+    at their full-size split counts and the 16-way split-K reduce."""
+    q, r, b = 32768, 384, 128
+    Y = inputs.uniform_matrix(q, r, seed=11)
+    Qg, Rg, info, flags = _factor(Y, b)
+    _compare(Y, b, Qg, Rg, info, flags)
+
+
+def test_square_n4096_factor_and_solve():
+    """Square FP64 workload at n = 4096, b = 128 (32 blocks), U[-1, 1]
+    entries and one right-hand side: factors, info, flags and x against the
+    oracle."""
+    n, b = 4096, 128
+    Y = inputs.uniform_matrix(n, n, seed=21)
+    rhs = inputs.uniform_vector(n, seed=22)
+    Yd = to_dev(Y)
+    Qd, Rd, info, flags = cqr.qr(Yd, b)
+    xd = cqr.solve(Qd, Rd, torch.from_numpy(rhs).cuda())
+    torch.cuda.synchronize()
+    Qg, Rg, xg = to_host(Qd), to_host(Rd), xd.cpu().numpy()
+    del Qd, Rd, Yd
+    ref = oracle.cgs_qr(Y, b)
+    _compare(Y, b, Qg, Rg, info, flags, ref)
+    xo, rc = oracle.qr_solve(ref["Q"], ref["R"], rhs)
+    assert rc == 0
+    tol = 8 * np.linalg.cond(Y) * n * EPS
+    np.testing.assert_allclose(xg, xo, rtol=0, atol=tol * np.abs(xo).max())
+    assert hpl_ratio(Y, xg, rhs) < 16
+
+
 def test_padded_leading_dimension():
     Y = inputs.uniform_matrix(200, 150, seed=3)
     Qg, Rg, info, flags = _factor(Y, 64, ld=211)
