@@ -128,6 +128,16 @@ int cqr_orth_against(int64_t q, int64_t b, int64_t s, double* Q, int64_t ldq, co
  */
 int cqr_set_wait_limit_us(int64_t us);
 
+/*
+ * Testing aid for the breakdown fallback of Section 3: from the next call on,
+ * cqr_factor and cqr_factor_mixed treat block blk (0-based) as if its
+ * Cholesky factorisation had broken down -- the block is redone by the CGS2
+ * fallback and info / block_flags report it -- so the fallback can be checked
+ * on inputs whose exact QR is known and well conditioned.  blk = -1 (the
+ * default) turns it off.  Returns -1 for blk < -1.  Process-wide.
+ */
+int cqr_set_forced_breakdown(int64_t blk);
+
 /* Bytes of device workspace cqr_solve needs for order n (returns -1 for n < 0). */
 int cqr_solve_workspace_size(int64_t n, size_t* bytes);
 
@@ -155,21 +165,28 @@ int cqr_solve(int64_t n, const double* Q, int64_t ldq, const double* R, int64_t 
  * Low-precision form of cqr_factor (not in the paper, which computes in IEEE
  * double): CGS-QR (Algorithm 3) with the projections H = P^T Q and the updates
  * Q -= P H of Algorithm 5 (S1/S2, S6/S7) on BF16 matrix cores with FP32
- * accumulation (prec = CQR_PREC_BF16); the working block, its Gram matrices,
- * Cholesky factors and triangular solves stay in FP64.
+ * accumulation (prec = CQR_PREC_BF16) or on FP8 E4M3 matrix cores with one
+ * power-of-two scale per operand column (prec = CQR_PREC_FP8); the working
+ * block, its Gram matrices, Cholesky factors and triangular solves stay in
+ * FP64.
  *   Y, ldy   in (device, FP64, 16-byte aligned, even ldy): q x r; not modified.
- *   Q, ldq   out (FP32): q x r with Q^T Q ~ I to BF16 accuracy.
+ *   Q, ldq   out (FP32): q x r with Q^T Q ~ I to BF16 (FP8) accuracy.
  *   R, ldr   out (FP32): r x r upper triangular.
  *   b        block width: a multiple of 16, at most 256 (a width above 128
  *            factors its Gram matrix as a 2 x 2 block).
- *   info     host, may be NULL: 0, or the 1-based index of the first block whose
- *            Cholesky factorisation broke down; then Q and R are not valid (this
- *            form has no CGS2 fallback; use cqr_factor).
- * Synchronises the stream once at the end.
+ *   info     device int32, may be NULL: 0, or the 1-based index of the first
+ *            block whose Cholesky factorisation broke down.  As in cqr_factor
+ *            (Section 3's fallback), such a block is redone column by column
+ *            by CGS2, here in FP64 arithmetic against the FP32 finished
+ *            columns, and the result is still a QR factorisation.
+ *            CQR_INFO_WAIT_ABANDONED as for cqr_factor.
+ *   block_flags  device int32, may be NULL, length ceil(r / b): CQR_FLAG_* bits.
+ * Asynchronous and kernels only, like cqr_factor (capturable).
  */
 int cqr_workspace_size_mixed(int64_t q, int64_t r, int64_t b, int prec, size_t* bytes);
 int cqr_factor_mixed(int64_t q, int64_t r, int64_t b, int prec, const double* Y, int64_t ldy, float* Q, int64_t ldq,
-                     float* R, int64_t ldr, void* work, size_t work_bytes, int32_t* info, void* stream);
+                     float* R, int64_t ldr, void* work, size_t work_bytes, int32_t* info, int32_t* block_flags,
+                     void* stream);
 
 /*
  * FP64 iterative refinement of Y x = rhs (square, n x n) with the factors of

@@ -24,7 +24,7 @@ PREC_BF16 = 1
 PREC_FP8 = 2
 
 __all__ = ["colmajor", "workspace_size", "qr", "qr_async", "orth", "orth_against", "solve", "solve_workspace_size",
-           "set_wait_limit_us", "qr_mixed", "solve_ir",
+           "set_wait_limit_us", "set_forced_breakdown", "qr_mixed", "qr_mixed_async", "solve_ir",
            "synth_uniform",
            "prof_enable", "prof_reset", "prof_query", "prof_names", "CqrError", "version"]
 
@@ -175,11 +175,13 @@ def solve(Q: torch.Tensor, R: torch.Tensor, rhs: torch.Tensor, work: torch.Tenso
     return x
 
 
-def qr_mixed(Y: torch.Tensor, b: int, prec: int = PREC_BF16, Q: torch.Tensor | None = None,
-             R: torch.Tensor | None = None, work: torch.Tensor | None = None):
+def qr_mixed_async(Y: torch.Tensor, b: int, prec: int = PREC_BF16, Q: torch.Tensor | None = None,
+                   R: torch.Tensor | None = None, work: torch.Tensor | None = None,
+                   info: torch.Tensor | None = None, flags: torch.Tensor | None = None):
     """Low-precision CGS-QR of column-major FP64 Y (not modified): BF16
     (prec=PREC_BF16) or FP8 E4M3 (prec=PREC_FP8) MFMA projections/updates, FP64
-    panel.  Returns (Q (FP32), R (FP32), info)."""
+    panel, enqueued with no host synchronisation.  Returns (Q (FP32), R (FP32),
+    info, flags) with info and flags int32 device tensors."""
     q, r = Y.shape
     if Q is None:
         Q = colmajor(q, r, device=Y.device, dtype=torch.float32)
@@ -189,11 +191,27 @@ def qr_mixed(Y: torch.Tensor, b: int, prec: int = PREC_BF16, Q: torch.Tensor | N
     _native.check(_native.lib().cqr_workspace_size_mixed(q, r, b, prec, ctypes.byref(n)), "cqr_workspace_size_mixed")
     if work is None:
         work = _workspace(int(n.value), Y.device)
-    info = ctypes.c_int32(0)
+    k = -(-r // b) if r else 0
+    info = _status(1, Y.device) if info is None else info
+    flags = _status(k, Y.device) if flags is None else flags
     rc = _native.lib().cqr_factor_mixed(q, r, b, prec, _ptr(Y), _ld(Y, "Y"), _ptr(Q), _ld32(Q, "Q"), _ptr(R),
-                                        _ld32(R, "R"), _ptr(work), work.numel(), ctypes.byref(info), _stream())
+                                        _ld32(R, "R"), _ptr(work), work.numel(), _ptr(info), _ptr(flags), _stream())
     _native.check(rc, "cqr_factor_mixed")
-    return Q, R, int(info.value)
+    return Q, R, info, flags
+
+
+def qr_mixed(Y: torch.Tensor, b: int, prec: int = PREC_BF16, Q: torch.Tensor | None = None,
+             R: torch.Tensor | None = None, work: torch.Tensor | None = None):
+    """qr_mixed_async, then info read back to the host (waits for the
+    stream).  Returns (Q (FP32), R (FP32), info)."""
+    Q, R, info, _ = qr_mixed_async(Y, b, prec, Q, R, work)
+    return Q, R, int(info[0].item())
+
+
+def set_forced_breakdown(blk: int) -> None:
+    """Testing aid: treat block blk (0-based) of later factorisations as broken
+    down (the CGS2 fallback redoes it); -1 turns it off."""
+    _native.check(_native.lib().cqr_set_forced_breakdown(int(blk)), "cqr_set_forced_breakdown")
 
 
 def solve_ir(Y: torch.Tensor, Q: torch.Tensor, R: torch.Tensor, rhs: torch.Tensor, maxiter: int = 50,

@@ -71,7 +71,13 @@ const char* const kRoleNames[ROLE_COUNT] = {"proj", "update", "gram", "trsm", "s
 std::mutex g_wait_mu;
 int64_t g_wait_us = 10 * 1000 * 1000;
 int g_clock_khz = 0;
+int64_t g_forced_blk = -1;  // block whose breakdown is forced (testing aid), -1 none
 }  // namespace
+
+int64_t forced_breakdown_block() {
+  std::lock_guard<std::mutex> lk(g_wait_mu);
+  return g_forced_blk;
+}
 
 const char* role_name(int role) { return (role >= 0 && role < ROLE_COUNT) ? kRoleNames[role] : nullptr; }
 
@@ -310,7 +316,7 @@ const char* cqr_version(void) { return "cqr 0.1 (gfx950, FP64 MFMA)"; }
 
 const char* cqr_status_string(int code) {
   if (code == CQR_OK) return "success";
-  if (code == CQR_ERR_UNSUPPORTED) return "unsupported parameters (block width must be 1..128, leading dimensions at most 4e6)";
+  if (code == CQR_ERR_UNSUPPORTED) return "unsupported parameters (block width must be 1..256, leading dimensions at most 4e6)";
   if (code == CQR_ERR_WORKSPACE) return "workspace missing or too small";
   if (code <= CQR_ERR_HIP_BASE) return hipGetErrorString((hipError_t)(CQR_ERR_HIP_BASE - code));
   if (code < 0 && code > -64) return "invalid argument (the negated return value is its 1-based position)";
@@ -348,19 +354,22 @@ int cqr_factor(int64_t q, int64_t r, int64_t b, double* Y, int64_t ldy, double* 
   if (rc) return rc;
   if (r == 0) return CQR_OK;
   CQR_TRY(zero_matrix(r, r, R, ldr, st));
+  const int64_t forced_blk = forced_breakdown_block();
   for (int64_t blk = 0; blk < k; ++blk) {
     const int64_t s = blk * b;
     const int64_t w = (r - s < b) ? (r - s) : b;
     double* Qj = Y + s * ldy;
     // The row-streaming form leaves the block intact on a breakdown; the
     // GEMM form works in place and keeps a copy for the fallback.
-    const bool keep = !tall_eligible(q, w, s);
+    const bool forced = blk == forced_blk;
+    const bool keep = forced || !tall_eligible(q, w, s);
     if (keep) CQR_TRY(copy_matrix(q, w, Qj, ldy, ws.save, q, ws.status, st));
     Seg seg{Y, ldy, s, R + s * ldr, ldr};
     rc = orth_block(q, w, Qj, ldy, &seg, s > 0 ? 1 : 0, R + s + s * ldr, ldr, ws, (int)blk, st);
     if (rc) return rc;
+    if (forced) CQR_TRY(force_breakdown(ws.status, (int)blk, st));
     CQR_TRY(cgs2_fallback(q, s, w, Y, ldy, Qj, ldy, R + s * ldr, ldr, R + s + s * ldr, ldr, keep ? ws.save : nullptr,
-                          ws.status, info, block_flags, (int)blk, ws.fb, st));
+                          q, ws.status, info, block_flags, (int)blk, ws.fb, st));
   }
   return CQR_OK;
 }
@@ -402,8 +411,15 @@ int cqr_orth_against(int64_t q, int64_t b, int64_t s, double* Q, int64_t ldq, co
   Seg seg{P, ldp, s, H, ldh};
   rc = orth_block(q, b, Q, ldq, &seg, s > 0 ? 1 : 0, R, ldr, ws, 0, st);
   if (rc) return rc;
-  CQR_TRY(cgs2_fallback(q, s, b, P, ldp, Q, ldq, H, ldh, R, ldr, keep ? ws.save : nullptr, ws.status, info, nullptr, 0,
-                        ws.fb, st));
+  CQR_TRY(cgs2_fallback(q, s, b, P, ldp, Q, ldq, H, ldh, R, ldr, keep ? ws.save : nullptr, q, ws.status, info, nullptr,
+                        0, ws.fb, st));
+  return CQR_OK;
+}
+
+int cqr_set_forced_breakdown(int64_t blk) {
+  if (blk < -1) return -1;
+  std::lock_guard<std::mutex> lk(g_wait_mu);
+  g_forced_blk = blk;
   return CQR_OK;
 }
 

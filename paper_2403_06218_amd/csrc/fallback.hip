@@ -33,9 +33,11 @@ namespace {
 constexpr int kFbThreads = 256;
 constexpr int kFbRowsPerThread = 1;  // target rows per thread when choosing the grid
 
+template <typename TP>
 struct FbArgs {
   int64_t q, s, w;
-  const double* P;  // q x s basis (ldp), may be null when s == 0
+  const TP* P;      // q x s basis (ldp), may be null when s == 0 (FP64, or the FP32 finished columns
+                    // of the low-precision form)
   int64_t ldp;
   double* Q;        // q x w block (ldq), in place
   int64_t ldq;
@@ -43,7 +45,8 @@ struct FbArgs {
   int64_t ldh;
   double* R;        // w x w triangle (ldr)
   int64_t ldr;
-  const double* save;  // q x w input copy (ld q), or null when the block is intact
+  const double* save;  // q x w input copy (ld ldsave), or null when the block is intact
+  int64_t ldsave;
   int* status;         // gate: status[0] != 0 means a breakdown in this block
   int32_t* info;       // device, may be null: first fallback block (1-based), or CQR_INFO_WAIT_ABANDONED
   int32_t* flags;      // device, may be null: flags[blk]
@@ -60,15 +63,36 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// x^T v over q rows for one wave: four accumulators per lane, combined in a
+// fixed order, then the wave sum.
+template <typename TX>
+__device__ __forceinline__ double column_dot(const TX* __restrict__ x, const double* __restrict__ v, int64_t q,
+                                             int lane) {
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int64_t i = lane;
+  for (; i + 192 < q; i += 256) {
+    acc[0] += (double)x[i] * v[i];
+    acc[1] += (double)x[i + 64] * v[i + 64];
+    acc[2] += (double)x[i + 128] * v[i + 128];
+    acc[3] += (double)x[i + 192] * v[i + 192];
+  }
+  for (int u = 0; i < q; i += 64, ++u) acc[u] += (double)x[i] * v[i];
+  return wave_sum((acc[0] + acc[1]) + (acc[2] + acc[3]));
+}
+
 // Grid barrier number `epoch` (1, 2, ...): every workgroup adds one arrival;
-// thread 0 waits until all gridDim.x * epoch arrivals are in (bounded).
-__device__ void grid_barrier(const FbArgs& a, unsigned epoch) {
+// thread 0 waits until all gridDim.x * epoch arrivals are in (bounded).  Once
+// any wait has been abandoned the result is void anyway, so later barriers do
+// not wait at all: the launch then ends within about one wait bound.
+template <typename TP>
+__device__ void grid_barrier(const FbArgs<TP>& a, unsigned epoch) {
   __syncthreads();
   if (threadIdx.x == 0) {
     __hip_atomic_fetch_add(&a.ctr[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned target = epoch * gridDim.x;
     const uint64_t t0 = wall_clock64();
     while (__hip_atomic_load(&a.ctr[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(&a.ctr[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
       if (wall_clock64() - t0 > a.wait_ticks) {
         __hip_atomic_store(&a.ctr[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
@@ -80,7 +104,8 @@ __device__ void grid_barrier(const FbArgs& a, unsigned epoch) {
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(kFbThreads) cgs2_fallback_kernel(FbArgs a) {
+template <typename TP>
+__global__ void __launch_bounds__(kFbThreads) cgs2_fallback_kernel(FbArgs<TP> a) {
   if (a.status[0] == 0) return;
   __shared__ double sRed[kFbThreads / 64];
   __shared__ double sNorm;
@@ -95,7 +120,7 @@ __global__ void __launch_bounds__(kFbThreads) cgs2_fallback_kernel(FbArgs a) {
   // Restore the block and clear its outputs.
   if (a.save)
     for (int64_t c = 0; c < a.w; ++c)
-      for (int64_t i = r0 + tid; i < r1; i += kFbThreads) a.Q[i + c * a.ldq] = a.save[i + c * a.q];
+      for (int64_t i = r0 + tid; i < r1; i += kFbThreads) a.Q[i + c * a.ldq] = a.save[i + c * a.ldsave];
   for (int64_t idx = (int64_t)blockIdx.x * kFbThreads + tid; idx < a.s * a.w; idx += G * kFbThreads)
     a.H[idx % a.s + (idx / a.s) * a.ldh] = 0.0;
   for (int64_t idx = (int64_t)blockIdx.x * kFbThreads + tid; idx < a.w * a.w; idx += G * kFbThreads)
@@ -114,17 +139,8 @@ __global__ void __launch_bounds__(kFbThreads) cgs2_fallback_kernel(FbArgs a) {
       double* h = t ? h2 : h1;
       // h = X^T v: one wave per basis column, four accumulators per lane.
       for (int64_t j = (int64_t)blockIdx.x * (kFbThreads / 64) + wave; j < nb; j += G * (kFbThreads / 64)) {
-        const double* x = (j < a.s) ? a.P + j * a.ldp : a.Q + (j - a.s) * a.ldq;
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        int64_t i = lane;
-        for (; i + 192 < a.q; i += 256) {
-          acc[0] += x[i] * v[i];
-          acc[1] += x[i + 64] * v[i + 64];
-          acc[2] += x[i + 128] * v[i + 128];
-          acc[3] += x[i + 192] * v[i + 192];
-        }
-        for (int u = 0; i < a.q; i += 64, ++u) acc[u] += x[i] * v[i];
-        const double d = wave_sum((acc[0] + acc[1]) + (acc[2] + acc[3]));
+        const double d = (j < a.s) ? column_dot(a.P + j * a.ldp, v, a.q, lane)
+                                   : column_dot(a.Q + (j - a.s) * a.ldq, v, a.q, lane);
         if (lane == 0) h[j] = d;
       }
       grid_barrier(a, ++epoch);
@@ -135,9 +151,9 @@ __global__ void __launch_bounds__(kFbThreads) cgs2_fallback_kernel(FbArgs a) {
         int64_t j = 0;
         for (; j + 4 <= a.s; j += 4) {
 #pragma unroll
-          for (int u = 0; u < 4; ++u) acc[u] += a.P[i + (j + u) * a.ldp] * h[j + u];
+          for (int u = 0; u < 4; ++u) acc[u] += (double)a.P[i + (j + u) * a.ldp] * h[j + u];
         }
-        for (; j < a.s; ++j) acc[0] += a.P[i + j * a.ldp] * h[j];
+        for (; j < a.s; ++j) acc[0] += (double)a.P[i + j * a.ldp] * h[j];
         for (int64_t k = 0; k < c; ++k) acc[1] += a.Q[i + k * a.ldq] * h[a.s + k];
         const double nv = v[i] - ((acc[0] + acc[1]) + (acc[2] + acc[3]));
         v[i] = nv;
@@ -209,15 +225,65 @@ int g_fb_grid = 0;  // resident workgroups of the fallback kernel (all CUs), fou
 
 int fb_max_grid() {
   if (g_fb_grid > 0) return g_fb_grid;
-  int dev = 0, cus = 0, per = 0;
+  int dev = 0, cus = 0, per64 = 0, per32 = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)cgs2_fallback_kernel, kFbThreads, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per64, (const void*)cgs2_fallback_kernel<double>, kFbThreads, 0) !=
       hipSuccess)
     return 0;
-  if (per < 1) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per32, (const void*)cgs2_fallback_kernel<float>, kFbThreads, 0) !=
+      hipSuccess)
+    return 0;
+  if (per64 < 1 || per32 < 1) return 0;
   g_fb_grid = cus;  // one workgroup per CU: every workgroup is resident at once
   return g_fb_grid;
+}
+
+__global__ void force_breakdown_kernel(int* status, int blk) {
+  if (status[0] == 0) {
+    status[0] = 1;
+    status[1] = blk;
+  }
+}
+
+template <typename TP>
+hipError_t launch_fallback(int64_t q, int64_t s, int64_t w, const TP* P, int64_t ldp, double* Q, int64_t ldq,
+                           double* H, int64_t ldh, double* R, int64_t ldr, const double* save, int64_t ldsave,
+                           int* status, int32_t* info, int32_t* flags, int blk, void* fbwork, hipStream_t st) {
+  if (q <= 0 || w <= 0) return hipSuccess;
+  int gmax = fb_max_grid();
+  if (gmax <= 0) return hipErrorInvalidConfiguration;
+  if (gmax > 1024) gmax = 1024;
+  int64_t g = (q + kFbThreads * kFbRowsPerThread - 1) / (kFbThreads * kFbRowsPerThread);
+  if (g > gmax) g = gmax;
+  if (g < 1) g = 1;
+  FbArgs<TP> a;
+  a.q = q;
+  a.s = s;
+  a.w = w;
+  a.P = P;
+  a.ldp = ldp > 0 ? ldp : 1;
+  a.Q = Q;
+  a.ldq = ldq;
+  a.H = H;
+  a.ldh = ldh > 0 ? ldh : 1;
+  a.R = R;
+  a.ldr = ldr;
+  a.save = save;
+  a.ldsave = ldsave > 0 ? ldsave : 1;
+  a.status = status;
+  a.info = info;
+  a.flags = flags;
+  a.blk = blk;
+  a.ctr = (unsigned*)fbwork;
+  a.part = (double*)((char*)fbwork + 256);
+  a.hbuf = (double*)((char*)fbwork + 256 + 1024 * sizeof(double));
+  a.wait_ticks = wait_limit_ticks();
+  const int slot = prof_begin(st);
+  hipLaunchKernelGGL(cgs2_fallback_kernel<TP>, dim3((unsigned)g), dim3(kFbThreads), 0, st, a);
+  const hipError_t e = hipGetLastError();
+  prof_end(slot, ROLE_FALLBACK, st, 0.0, 0.0);
+  return e;
 }
 
 }  // namespace
@@ -231,41 +297,23 @@ size_t fallback_workspace_bytes(int64_t sw) {
 }
 
 hipError_t cgs2_fallback(int64_t q, int64_t s, int64_t w, const double* P, int64_t ldp, double* Q, int64_t ldq,
-                         double* H, int64_t ldh, double* R, int64_t ldr, const double* save, int* status,
-                         int32_t* info, int32_t* flags, int blk, void* fbwork, hipStream_t st) {
-  if (q <= 0 || w <= 0) return hipSuccess;
-  int gmax = fb_max_grid();
-  if (gmax <= 0) return hipErrorInvalidConfiguration;
-  if (gmax > 1024) gmax = 1024;
-  int64_t g = (q + kFbThreads * kFbRowsPerThread - 1) / (kFbThreads * kFbRowsPerThread);
-  if (g > gmax) g = gmax;
-  if (g < 1) g = 1;
-  FbArgs a;
-  a.q = q;
-  a.s = s;
-  a.w = w;
-  a.P = P;
-  a.ldp = ldp > 0 ? ldp : 1;
-  a.Q = Q;
-  a.ldq = ldq;
-  a.H = H;
-  a.ldh = ldh > 0 ? ldh : 1;
-  a.R = R;
-  a.ldr = ldr;
-  a.save = save;
-  a.status = status;
-  a.info = info;
-  a.flags = flags;
-  a.blk = blk;
-  a.ctr = (unsigned*)fbwork;
-  a.part = (double*)((char*)fbwork + 256);
-  a.hbuf = (double*)((char*)fbwork + 256 + 1024 * sizeof(double));
-  a.wait_ticks = wait_limit_ticks();
-  const int slot = prof_begin(st);
-  hipLaunchKernelGGL(cgs2_fallback_kernel, dim3((unsigned)g), dim3(kFbThreads), 0, st, a);
-  const hipError_t e = hipGetLastError();
-  prof_end(slot, ROLE_FALLBACK, st, 0.0, 0.0);
-  return e;
+                         double* H, int64_t ldh, double* R, int64_t ldr, const double* save, int64_t ldsave,
+                         int* status, int32_t* info, int32_t* flags, int blk, void* fbwork, hipStream_t st) {
+  return launch_fallback<double>(q, s, w, P, ldp, Q, ldq, H, ldh, R, ldr, save, ldsave, status, info, flags, blk,
+                                 fbwork, st);
+}
+
+hipError_t cgs2_fallback_f32basis(int64_t q, int64_t s, int64_t w, const float* P, int64_t ldp, double* Q,
+                                  int64_t ldq, double* H, int64_t ldh, double* R, int64_t ldr, const double* save,
+                                  int64_t ldsave, int* status, int32_t* info, int32_t* flags, int blk, void* fbwork,
+                                  hipStream_t st) {
+  return launch_fallback<float>(q, s, w, P, ldp, Q, ldq, H, ldh, R, ldr, save, ldsave, status, info, flags, blk,
+                                fbwork, st);
+}
+
+hipError_t force_breakdown(int* status, int blk, hipStream_t st) {
+  hipLaunchKernelGGL(force_breakdown_kernel, dim3(1), dim3(1), 0, st, status, blk);
+  return hipGetLastError();
 }
 
 }  // namespace cqr

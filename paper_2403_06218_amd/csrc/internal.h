@@ -111,15 +111,25 @@ hipError_t zero_matrix(int64_t rows, int64_t cols, double* X, int64_t ldx, hipSt
 // Breakdown fallback (Section 3): redo the block Q (q x w, ldq) column by
 // column by CGS2 against P (q x s, ldp) and its own earlier columns, in one
 // launch gated on status[0] != 0 (an empty launch otherwise).  Restores the
-// block from `save` (q x w, ld q) first when save != NULL.  Writes H (s x w,
+// block from `save` (q x w, ldsave) first when save != NULL.  Writes H (s x w,
 // ldh) and R (w x w, ldr); sets flags[blk] and info (first block, 1-based) when
 // those are not NULL, then clears status.  `fbwork` holds
 // fallback_workspace_bytes(s + w) bytes whose first 256 bytes (the counters)
-// are zero before the first call; the kernel leaves them zero.
+// are zero before the first call; the kernel leaves them zero.  The _f32basis
+// form takes the FP32 finished columns of the low-precision form as P (FP64
+// arithmetic).
 size_t fallback_workspace_bytes(int64_t sw);
 hipError_t cgs2_fallback(int64_t q, int64_t s, int64_t w, const double* P, int64_t ldp, double* Q, int64_t ldq,
-                         double* H, int64_t ldh, double* R, int64_t ldr, const double* save, int* status,
-                         int32_t* info, int32_t* flags, int blk, void* fbwork, hipStream_t st);
+                         double* H, int64_t ldh, double* R, int64_t ldr, const double* save, int64_t ldsave,
+                         int* status, int32_t* info, int32_t* flags, int blk, void* fbwork, hipStream_t st);
+hipError_t cgs2_fallback_f32basis(int64_t q, int64_t s, int64_t w, const float* P, int64_t ldp, double* Q,
+                                  int64_t ldq, double* H, int64_t ldh, double* R, int64_t ldr, const double* save,
+                                  int64_t ldsave, int* status, int32_t* info, int32_t* flags, int blk, void* fbwork,
+                                  hipStream_t st);
+// Sets status = {1, blk} when no breakdown is recorded (the forced breakdown
+// of cqr_set_forced_breakdown); forced_breakdown_block() is that block, or -1.
+hipError_t force_breakdown(int* status, int blk, hipStream_t st);
+int64_t forced_breakdown_block();
 
 // Sparse matrix in CSR form with its transpose (also CSR), for the products
 // A X and A^T X of the truncated SVD.  Row pointers and column indices are

@@ -52,6 +52,7 @@ struct MixedWork {
   double* cmax;     // b: column maxima
   float* part;      // split-K partial sums
   size_t part_cap;
+  void* fb;         // breakdown fallback workspace (counters first; zero at the start of a call)
   int64_t qp, rp;
 };
 
@@ -97,6 +98,7 @@ size_t mixed_layout(int64_t q, int64_t r, int64_t b, int prec, char* base, Mixed
   }
   o->part_cap = (size_t)16 << 20;
   o->part = (float*)take(o->part_cap * 4);
+  o->fb = take(fallback_workspace_bytes(r > b ? r : b));
   return off;
 }
 
@@ -390,6 +392,13 @@ gemv_t_f32_kernel(int64_t n, const float* __restrict__ Q, int64_t ldq, const dou
   if (lane == 0) y[j] = acc;
 }
 
+// info = 0 and the k block flags = 0 (device outputs; NULL skips them).
+__global__ void init_info_kernel(int32_t* info, int32_t* flags, int64_t k) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0 && info) info[0] = 0;
+  if (flags && i < k) flags[i] = 0;
+}
+
 __global__ void __launch_bounds__(256) axpy_kernel(int64_t n, const double* __restrict__ d, double* __restrict__ x) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) x[i] += d[i];
@@ -397,9 +406,25 @@ __global__ void __launch_bounds__(256) axpy_kernel(int64_t n, const double* __re
 
 // ---------------------------------------------------------------- factor
 
+// Breakdown fallback of one block (Section 3): when a Cholesky factorisation
+// of the block broke down (or the block's breakdown is forced), the block is
+// restored from Y and redone column by column by CGS2 in FP64 arithmetic
+// against the FP32 finished columns, writing ws.Qj, the projections ws.H and
+// the triangle ws.Rjj; info and flags record it and the status word is
+// cleared, so the block's remaining steps run.  An empty launch otherwise.
+hipError_t block_fallback(int64_t q, int64_t w, int64_t s, const double* Yj, int64_t ldy, const float* Q32,
+                          int64_t ldq, const MixedWork& ws, int blk, int32_t* info, int32_t* flags, hipStream_t st) {
+  if (blk == forced_breakdown_block()) {
+    hipError_t e = force_breakdown(ws.status, blk, st);
+    if (e != hipSuccess) return e;
+  }
+  return cgs2_fallback_f32basis(q, s, w, Q32, ldq, ws.Qj, q, ws.H, ws.rp, ws.Rjj, w, Yj, ldy, ws.status, info, flags,
+                                blk, ws.fb, st);
+}
+
 // One column block of the BF16 form (see the file comment).
 int mixed_block(int64_t q, int64_t w, int64_t s, const double* Yj, int64_t ldy, float* Q32, int64_t ldq, float* R32,
-                int64_t ldr, const MixedWork& ws, int blk, hipStream_t st) {
+                int64_t ldr, const MixedWork& ws, int blk, int32_t* info, int32_t* flags, hipStream_t st) {
   const int* gate = ws.status;
   const double dq = (double)q, dw = (double)w, ds = (double)s;
   const int64_t sp = up(s, 64);
@@ -429,11 +454,12 @@ int mixed_block(int64_t q, int64_t w, int64_t s, const double* Yj, int64_t ldy, 
     MX_TRY(gemm_nn(ROLE_TRSM, q, w, w, 1.0, X, q, pass == 0 ? ws.XT1 : ws.XT2, w, 0.0, pass == 0 ? ws.T : ws.Qj, q,
                    gate, st, dw * dw * dq));
   }
-  // S11 R_jj = Lb^T L^T, S12 H = H + Hb L^T, in FP64; then R (FP32) and the
-  // finished columns.
+  // S11 R_jj = Lb^T L^T, S12 H = H + Hb L^T, in FP64; then the fallback
+  // (a breakdown redoes the block by CGS2), R (FP32) and the finished columns.
   MX_TRY(gemm_nn(ROLE_SMALL, w, w, w, 1.0, ws.LT2, w, ws.LT1, w, 0.0, ws.Rjj, w, gate, st, dw * dw * dw));
+  if (s > 0) MX_TRY(gemm_nn(ROLE_SMALL, s, w, w, 1.0, ws.Hb, ws.rp, ws.LT1, w, 1.0, ws.H, ws.rp, gate, st, dw * ds));
+  MX_TRY(block_fallback(q, w, s, Yj, ldy, Q32, ldq, ws, blk, info, flags, st));
   if (s > 0) {
-    MX_TRY(gemm_nn(ROLE_SMALL, s, w, w, 1.0, ws.Hb, ws.rp, ws.LT1, w, 1.0, ws.H, ws.rp, gate, st, dw * ds));
     hipLaunchKernelGGL(to_f32_kernel, dim3(grid_of(s * w)), dim3(256), 0, st, s, w, ws.H, ws.rp, R32 + s * ldr, ldr,
                        gate);
     MX_TRY(hipGetLastError());
@@ -450,7 +476,8 @@ int mixed_block(int64_t q, int64_t w, int64_t s, const double* Yj, int64_t ldy, 
 // One column block of the FP8 form: as mixed_block, with the projections and
 // updates on FP8 operands scaled per column.
 int mixed_block_fp8(int64_t q, int64_t w, int64_t s, const double* Yj, int64_t ldy, float* Q32, int64_t ldq,
-                    float* R32, int64_t ldr, const MixedWork& ws, int blk, hipStream_t st) {
+                    float* R32, int64_t ldr, const MixedWork& ws, int blk, int32_t* info, int32_t* flags,
+                    hipStream_t st) {
   const int* gate = ws.status;
   const double dq = (double)q, dw = (double)w, ds = (double)s;
   const int64_t sp = up(s, 128);
@@ -486,8 +513,9 @@ int mixed_block_fp8(int64_t q, int64_t w, int64_t s, const double* Yj, int64_t l
                    gate, st, dw * dw * dq));
   }
   MX_TRY(gemm_nn(ROLE_SMALL, w, w, w, 1.0, ws.LT2, w, ws.LT1, w, 0.0, ws.Rjj, w, gate, st, dw * dw * dw));
+  if (s > 0) MX_TRY(gemm_nn(ROLE_SMALL, s, w, w, 1.0, ws.Hb, ws.rp, ws.LT1, w, 1.0, ws.H, ws.rp, gate, st, dw * ds));
+  MX_TRY(block_fallback(q, w, s, Yj, ldy, Q32, ldq, ws, blk, info, flags, st));
   if (s > 0) {
-    MX_TRY(gemm_nn(ROLE_SMALL, s, w, w, 1.0, ws.Hb, ws.rp, ws.LT1, w, 1.0, ws.H, ws.rp, gate, st, dw * ds));
     hipLaunchKernelGGL(to_f32_kernel, dim3(grid_of(s * w)), dim3(256), 0, st, s, w, ws.H, ws.rp, R32 + s * ldr, ldr,
                        gate);
     MX_TRY(hipGetLastError());
@@ -523,7 +551,8 @@ int cqr_workspace_size_mixed(int64_t q, int64_t r, int64_t b, int prec, size_t* 
 }
 
 int cqr_factor_mixed(int64_t q, int64_t r, int64_t b, int prec, const double* Y, int64_t ldy, float* Q, int64_t ldq,
-                     float* R, int64_t ldr, void* work, size_t work_bytes, int32_t* info, void* stream) {
+                     float* R, int64_t ldr, void* work, size_t work_bytes, int32_t* info, int32_t* block_flags,
+                     void* stream) {
   if (q < 0) return -1;
   if (r < 0 || r > q) return -2;
   if (b < 1) return -3;
@@ -536,31 +565,32 @@ int cqr_factor_mixed(int64_t q, int64_t r, int64_t b, int prec, const double* Y,
   if (!R && r > 0) return -9;
   if (ldr < (r > 1 ? r : 1)) return -10;
   if (reinterpret_cast<uintptr_t>(Y) & 15) return CQR_ERR_UNSUPPORTED;
-  if (info) *info = 0;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t k = (r + b - 1) / b;
+  if (info || block_flags) {
+    const int64_t nk = k > 1 ? k : 1;
+    hipLaunchKernelGGL(init_info_kernel, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, st, info, block_flags, k);
+    MX_TRY(hipGetLastError());
+  }
   if (r == 0) return CQR_OK;
   const size_t need = mixed_layout(q, r, b, prec, nullptr, nullptr);
   if (!work || work_bytes < need) return CQR_ERR_WORKSPACE;
   MixedWork ws;
   mixed_layout(q, r, b, prec, (char*)work, &ws);
-  hipStream_t st = (hipStream_t)stream;
   // Zero the whole workspace: the BF16 buffers rely on zero padding and on
   // not-yet-finished columns reading as zero.
   hipLaunchKernelGGL(fill_kernel, dim3(grid_of((int64_t)need)), dim3(256), 0, st, (int64_t)need, (char*)work);
   MX_TRY(hipGetLastError());
   hipLaunchKernelGGL(zero_f32_kernel, dim3(grid_of(r * r)), dim3(256), 0, st, r, r, R, ldr);
   MX_TRY(hipGetLastError());
-  const int64_t k = (r + b - 1) / b;
   for (int64_t blk = 0; blk < k; ++blk) {
     const int64_t s = blk * b;
     const int64_t w = (r - s < b) ? r - s : b;
-    const int rc = (prec == CQR_PREC_FP8) ? mixed_block_fp8(q, w, s, Y + s * ldy, ldy, Q, ldq, R, ldr, ws, (int)blk, st)
-                                          : mixed_block(q, w, s, Y + s * ldy, ldy, Q, ldq, R, ldr, ws, (int)blk, st);
+    const int rc = (prec == CQR_PREC_FP8)
+                       ? mixed_block_fp8(q, w, s, Y + s * ldy, ldy, Q, ldq, R, ldr, ws, (int)blk, info, block_flags, st)
+                       : mixed_block(q, w, s, Y + s * ldy, ldy, Q, ldq, R, ldr, ws, (int)blk, info, block_flags, st);
     if (rc) return rc;
   }
-  int stv[2] = {0, 0};
-  MX_TRY(hipStreamSynchronize(st));
-  MX_TRY(hipMemcpy(stv, ws.status, sizeof(stv), hipMemcpyDeviceToHost));
-  if (stv[0] != 0 && info) *info = stv[1] + 1;
   return CQR_OK;
 }
 

@@ -17,7 +17,7 @@ import torch
 import oracle
 import paper_2403_06218_amd as cqr
 from paper_2403_06218_amd import inputs
-from gpu_util import EPS, orth_ratio, recon_ratio, to_dev, to_host
+from gpu_util import EPS, hpl_ratio, orth_ratio, recon_ratio, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -166,3 +166,108 @@ def test_fallback_reports_abandoned_wait():
     _, _, info, flags = cqr.qr(to_dev(Y), 8)
     ref = oracle.cgs_qr(Y, 8)
     assert info == ref["info"] == 2 and flags == list(ref["block_flags"]) == [0, 3]
+
+
+def _forced(blk):
+    cqr.set_forced_breakdown(blk)
+
+
+@pytest.mark.parametrize("q,r,b,blk", [(600, 600, 64, 3), (1000, 700, 256, 1), (20000, 64, 16, 2)])
+def test_forced_breakdown_matches_unique_qr(q, r, b, blk):
+    """A breakdown forced from the host in block blk: the block is redone by
+    the CGS2 fallback.  The thin QR with positive diagonal is unique, so the
+    result still matches the oracle's factorisation of the same input; info
+    and the flags report the fallback.  (q = 20000, b = 16 takes the
+    row-streaming path, which then keeps a copy of the block.)"""
+    Y = inputs.uniform_matrix(q, r, seed=q + blk)
+    try:
+        _forced(blk)
+        Q, R, info, flags = cqr.qr(to_dev(Y), b)
+    finally:
+        _forced(-1)
+    ref = oracle.cgs_qr(Y, b)
+    assert ref["info"] == 0
+    assert info == blk + 1
+    want = [0] * len(flags)
+    want[blk] = 1
+    assert flags == want
+    Qg, Rg = to_host(Q), to_host(R)
+    tol = 8 * np.linalg.cond(Y) * q * EPS
+    np.testing.assert_allclose(Qg, ref["Q"], rtol=0, atol=tol)
+    np.testing.assert_allclose(Rg, ref["R"], rtol=0, atol=tol * np.linalg.norm(Y, 2))
+    assert recon_ratio(Y, Qg, Rg) < 16 and orth_ratio(Qg) < 16
+
+
+@pytest.mark.parametrize("prec", [cqr.PREC_BF16, cqr.PREC_FP8])
+def test_mixed_forced_breakdown_refines_to_oracle_solution(prec):
+    """The precision form's fallback: a breakdown forced in block 5 of a
+    diagonally dominant n = 2048 matrix (b = 128) is redone by CGS2 in FP64
+    against the FP32 finished columns; info/flags report it on the device;
+    the refinement still reaches the FP64 HPL bar and the oracle's x."""
+    n, b, blk = 2048, 128, 5
+    Y = inputs.diag_dominant(n, seed=51)
+    rhs = inputs.uniform_vector(n, seed=52)
+    Yd = to_dev(Y)
+    try:
+        _forced(blk)
+        Q, R, info, flags = cqr.qr_mixed_async(Yd, b, prec=prec)
+        torch.cuda.synchronize()
+    finally:
+        _forced(-1)
+    assert int(info[0]) == blk + 1
+    fl = flags.cpu().tolist()
+    assert fl[blk] == 1 and sum(fl) == 1
+    x, iters, res = cqr.solve_ir(Yd, Q, R, torch.from_numpy(rhs).cuda(), maxiter=30, tol=16.0)
+    xh = x.cpu().numpy()
+    assert res < 16 and hpl_ratio(Y, xh, rhs) < 16
+    ref = oracle.cgs_qr(Y, b)
+    xo, _ = oracle.qr_solve(ref["Q"], ref["R"], rhs)
+    assert np.abs(xh - xo).max() <= 16 * np.linalg.cond(Y) * n * EPS * np.abs(xo).max()
+    # The redone block is orthonormal to FP32 accuracy and orthogonal to the earlier columns.
+    Qh = np.asfortranarray(Q.t().cpu().numpy().T).astype(np.float64)
+    blkQ = Qh[:, blk * b:(blk + 1) * b]
+    assert np.abs(blkQ.T @ blkQ - np.eye(b)).max() < 1e-5
+    assert np.abs(Qh[:, :blk * b].T @ blkQ).max() < 1e-2
+
+
+def test_mixed_factor_graph_replay_matches_eager():
+    """cqr_factor_mixed is kernels only: captured in a hipGraph (with a forced
+    fallback block), every replay gives the eager call's bits and info."""
+    n, b = 1024, 128
+    Yd = to_dev(inputs.diag_dominant(n, seed=53))
+    Q = cqr.colmajor(n, n, dtype=torch.float32)
+    R = cqr.colmajor(n, n, dtype=torch.float32)
+    import ctypes
+    nb = ctypes.c_size_t(0)
+    cqr._native.lib().cqr_workspace_size_mixed(n, n, b, cqr.PREC_BF16, ctypes.byref(nb))
+    work = torch.empty(int(nb.value), dtype=torch.uint8, device="cuda")
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    flags = torch.zeros(n // b, dtype=torch.int32, device="cuda")
+    try:
+        _forced(2)
+        cqr.qr_mixed_async(Yd, b, Q=Q, R=R, work=work, info=info, flags=flags)
+        torch.cuda.synchronize()
+        Qe, Re, ie, fe = Q.clone(), R.clone(), info.clone(), flags.clone()
+        assert int(ie[0]) == 3
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            cqr.qr_mixed_async(Yd, b, Q=Q, R=R, work=work, info=info, flags=flags)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            cqr.qr_mixed_async(Yd, b, Q=Q, R=R, work=work, info=info, flags=flags)
+    finally:
+        _forced(-1)
+    for _ in range(3):
+        cqr.qr(to_dev(inputs.uniform_matrix(300, 64, seed=54)), 16)
+        Q.fill_(float("nan"))
+        R.fill_(float("nan"))
+        info.fill_(-9)
+        flags.fill_(-9)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(Q, Qe) and torch.equal(R, Re)
+        assert torch.equal(info, ie) and torch.equal(flags, fe)
