@@ -39,6 +39,7 @@ def parse():
     p.add_argument("--n", type=int, default=32768)
     p.add_argument("--b", type=int, default=0, help="block width of the FP64 form; 0 = autotune over --b-candidates")
     p.add_argument("--b-candidates", default="64,128,256")
+    p.add_argument("--c3-n", type=int, default=0, help="order of the diagonally dominant comparison (0 = --n)")
     p.add_argument("--c3-fp64-steps", type=int, default=3,
                    help="timed FP64 steps on the diagonally dominant matrix (the speed-up's denominator)")
     p.add_argument("--seed", type=int, default=0)
@@ -536,17 +537,18 @@ def bench_c3(cqr, torch, n: int, b64: int, bmix: int, K: int, W: int, K64: int, 
 
     times, infos = [], []
     x64 = None
-    for i in range(1 + K64):
+    for i in range(1 + K64 if K64 > 0 else 0):
         Yw.copy_(Y)
         torch.cuda.synchronize()
         ms, (info, x64) = _event_ms(torch, fp64_step)
         if i:
             times.append(ms)
             infos.append(int(info[0]))
-    fp64_ms = float(np.median(times))
+    fp64_ms = float(np.median(times)) if times else None
     flops = costmodel.ca3(b64, n, n) + costmodel.solve_flops(n)
-    out["fp64"] = {"b": b64, "ms_per_step": round(fp64_ms, 2), "value": round(flops / (fp64_ms * 1e-3) / 1e9, 2),
-                   "unit": "GFLOP/s", "info": infos, "hpl_scaled_residual": hpl_residual(torch, Y, x64, rhs)}
+    if fp64_ms:
+        out["fp64"] = {"b": b64, "ms_per_step": round(fp64_ms, 2), "value": round(flops / (fp64_ms * 1e-3) / 1e9, 2),
+                       "unit": "GFLOP/s", "info": infos, "hpl_scaled_residual": hpl_residual(torch, Y, x64, rhs)}
     del Yw, R, work, swork
     torch.cuda.empty_cache()
 
@@ -591,9 +593,9 @@ def bench_c3(cqr, torch, n: int, b64: int, bmix: int, K: int, W: int, K64: int, 
                      "frac": round(lp[dom]["tflops"] / peak, 4), "avg_launch_ms": round(lp[dom]["ms"] /
                                                                                        lp[dom]["launches"], 4)}
                     if dom else None)
-        rel = float((xm - x64).abs().max() / x64.abs().max())
+        rel = float((xm - x64).abs().max() / x64.abs().max()) if x64 is not None else None
         out[name] = {"b": bmix, "value": round(flops / el / 1e9, 2), "unit": "GFLOP/s", "ms_per_step": round(el * 1e3, 2),
-                     "speedup_vs_fp64_same_matrix": round(fp64_ms / (el * 1e3), 3),
+                     "speedup_vs_fp64_same_matrix": round(fp64_ms / (el * 1e3), 3) if fp64_ms else None,
                      "ir_iterations": [o[1] for o in res_list], "hpl_scaled_residual": [o[2] for o in res_list],
                      "info": [int(o[0][0]) for o in res_list], "max_rel_diff_x_vs_fp64_form": rel,
                      "roofline": roofline, "factor_ms_profiled": round(fms, 2),
@@ -617,7 +619,7 @@ def summary(out: dict) -> dict:
                      "hpl": out["checks"]["hpl_scaled_residual"], "valid": out["checks"]["valid"]}
     c3 = out.get("c3")
     if c3:
-        s["c3_fp64_ms"] = c3["fp64"]["ms_per_step"]
+        s["c3_fp64_ms"] = c3["fp64"]["ms_per_step"] if "fp64" in c3 else None
         for k in ("bf16", "fp8"):
             if k in c3:
                 v = c3[k]
@@ -667,7 +669,7 @@ def main():
         out, b = bench_fp64(args, torch, cqr, costmodel, inputs)
     if not args.no_mixed:
         torch.cuda.empty_cache()
-        out["c3"] = bench_c3(cqr, torch, n, b, args.mixed_b, K, W, args.c3_fp64_steps, args.seed)
+        out["c3"] = bench_c3(cqr, torch, args.c3_n or n, b, args.mixed_b, K, W, args.c3_fp64_steps, args.seed)
     if not args.no_batched:
         out["batched"] = bench_batched(torch, K, W, args.seed, not args.no_tune)
     if not args.no_adjoint:

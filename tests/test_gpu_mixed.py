@@ -205,3 +205,54 @@ def test_mixed_permutation_bit_exact(prec, n, b):
     assert info == 0
     assert np.array_equal(_host32(Q), Y)
     assert np.array_equal(_host32(R), np.eye(n))
+
+
+@pytest.mark.parametrize("prec", [cqr.PREC_BF16, cqr.PREC_FP8])
+def test_c3_n65536_properties(prec):
+    """The largest mixed-precision workload, n = 65536 (b = 256, Y 34 GB):
+    size-independent checks only.  Freivalds probes of the reconstruction
+    ||Y z - Q (R z)|| / (||Y||_F ||z||) for 4 Gaussian z, orthogonality of 64
+    sampled columns of Q, the exact upper triangle with a positive diagonal
+    (sampled rows), and the refined solution under the FP64 HPL bar with the
+    residual recomputed here."""
+    n, b = 65536, 256
+    u = U_BF16 if prec == cqr.PREC_BF16 else U_FP8
+    Y = cqr.colmajor(n, n)
+    cqr.synth_uniform(Y, 91, -0.5, 0.5)
+    Y.diagonal().zero_()
+    rs = torch.zeros(n, dtype=torch.float64, device="cuda")
+    for j in range(0, n, 4096):
+        rs += Y[:, j:j + 4096].abs().sum(dim=1)
+    Y.diagonal().copy_(rs + 1.0)
+    rhs = torch.empty(n, dtype=torch.float64, device="cuda")
+    cqr.synth_uniform(rhs.view(n, 1), 92)
+    Q, R, info, flags = cqr.qr_mixed_async(Y, b, prec=prec)
+    torch.cuda.synchronize()
+    assert int(info[0]) == 0 and not flags.any()
+    g = torch.Generator(device="cuda").manual_seed(93)
+    Z = torch.randn(n, 4, dtype=torch.float64, device="cuda", generator=g)
+    ynorm = float(torch.linalg.norm(Y))
+    RZ = torch.zeros(n, 4, dtype=torch.float64, device="cuda")
+    QRZ = torch.zeros(n, 4, dtype=torch.float64, device="cuda")
+    for j in range(0, n, 8192):  # R Z and Q (R Z) in column slabs (FP64 accumulation)
+        RZ += R[:, j:j + 8192].double() @ Z[j:j + 8192]
+    for j in range(0, n, 8192):
+        QRZ += Q[:, j:j + 8192].double() @ RZ[j:j + 8192]
+    rec = float(torch.linalg.norm(Y @ Z - QRZ) / (ynorm * torch.linalg.norm(Z)))
+    assert rec < 2 * u, rec
+    cols = torch.from_numpy(np.sort(np.random.default_rng(94).choice(n, 64, replace=False))).cuda()
+    Qc = Q[:, cols].double()
+    G = Qc.t() @ Qc
+    G.diagonal().sub_(1.0)
+    assert float(G.abs().max()) < 4 * u
+    rows = cols
+    Rr = R[rows].double()
+    jj = torch.arange(n, device="cuda")
+    assert not (Rr * (jj[None, :] < rows[:, None])).any()
+    assert (R.diagonal()[rows] > 0).all()
+    del Qc, G, Rr, RZ, QRZ
+    x, iters, res = cqr.solve_ir(Y, Q, R, rhs, maxiter=50, tol=16.0)
+    assert res < 16 and iters <= 10, (res, iters)
+    r = (Y @ x - rhs).abs().max()
+    hpl = float(r / ((rs + Y.diagonal().abs()).max() * x.abs().max() * n * EPS))
+    assert hpl < 16, hpl

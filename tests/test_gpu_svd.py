@@ -54,7 +54,7 @@ def test_small_svd_matches_lapack(r, kind):
     Ug, sg, Vg = _h(U), _h(s), _h(V)
     ref = np.linalg.svd(B, compute_uv=False)
     nb = np.linalg.norm(B, 2)
-    assert sweeps > 0
+    assert sweeps > 0 if r > 1 else sweeps == 0  # a 1 x 1 matrix needs no rotation
     assert (np.diff(sg) <= 0).all()
     np.testing.assert_allclose(sg, ref, rtol=0, atol=16 * r * EPS * nb)
     assert np.linalg.norm(B - (Ug * sg) @ Vg.T) <= 16 * r * EPS * np.linalg.norm(B)
@@ -80,9 +80,12 @@ def _weyl(nsteps, m, nA):
     return 2.0 * nsteps * m * EPS * nA
 
 
-def _compare_triplets(Ug, sg, Vg, Uo, so, Vo, tol, count):
-    np.testing.assert_allclose(sg, so, rtol=0, atol=tol)
-    for j in range(count):
+def _compare_triplets(Ug, sg, Vg, Uo, so, Vo, tol, idx):
+    """Triplets idx of the GPU run against the oracle's: values within the
+    Weyl bound, vectors (up to sign) within Wedin's bound where separated."""
+    idx = list(idx)
+    np.testing.assert_allclose(sg[idx], so[idx], rtol=0, atol=tol)
+    for j in idx:
         gap = min([abs(so[j] - so[i]) for i in range(len(so)) if i != j] + [so[j]])
         if gap < 1e3 * tol:
             continue
@@ -90,6 +93,26 @@ def _compare_triplets(Ug, sg, Vg, Uo, so, Vo, tol, count):
         for G, O in ((Ug, Uo), (Vg, Vo)):
             d = min(np.abs(G[:, j] - O[:, j]).max(), np.abs(G[:, j] + O[:, j]).max())
             assert d <= bound, (j, d, bound)
+
+
+def _check_rayleigh_ritz(A, Ug, sg, Vg, r):
+    """Properties of any correct Rayleigh-Ritz output, converged or not:
+    U and V orthonormal and U^T A V = diag(sigma) (the bases are exact
+    projections, P_k-bar^T A P_k = B_k), each to a small multiple of r eps
+    (||A||).  The oracle's own runs stay below 5 r eps."""
+    nA = sg[0]
+    assert np.abs(Ug.T @ Ug - np.eye(r)).max() <= 64 * r * EPS
+    assert np.abs(Vg.T @ Vg - np.eye(r)).max() <= 64 * r * EPS
+    assert np.abs(Ug.T @ (A @ Vg) - np.diag(sg)).max() <= 64 * r * EPS * nA
+
+
+def _converged(A, ref, thresh=1e-8):
+    """Indices of the oracle's triplets whose residual is below thresh: only
+    these are determined by A and the start block; the unconverged Ritz
+    values of a Krylov run on a graded spectrum depend on rounding (two
+    correct runs agree on them only loosely)."""
+    res = osvd.residuals(A, ref["U"], ref["sigma"], ref["V"])
+    return np.nonzero(res < thresh)[0], res
 
 
 @pytest.mark.parametrize("p", [1, 3])
@@ -105,13 +128,17 @@ def test_lancsvd_matches_oracle(p):
     assert info == sum(1 for c in ref["codes"] if c != 0) == 0
     k = r // b
     tol = _weyl(p * (4 * k + 2) + 2, m, sig[0])
-    _compare_triplets(Ug, sg, Vg, ref["U"], ref["sigma"], ref["V"], tol, r)
-    # The 10 leading values and residuals reach rounding level (constructed spectrum).
+    conv, ref_res = _converged(A, ref)
+    assert len(conv) >= 10 and (conv[:10] == np.arange(10)).all()
+    _compare_triplets(Ug, sg, Vg, ref["U"], ref["sigma"], ref["V"], tol, conv)
+    _check_rayleigh_ritz(A, Ug, sg, Vg, r)
+    # The 10 leading values reach rounding level (constructed spectrum) and
+    # their residuals follow the oracle's.
     assert np.abs(sg[:10] - sig[:10]).max() < 1e-13 * sig[0]
     res = _h(svd.residuals(to_dev(A), U, s, V, 10))
-    ref_res = osvd.residuals(A, Ug, sg, Vg, 10)
-    np.testing.assert_allclose(res, ref_res, rtol=1e-6, atol=1e-15)
-    assert res.max() < 1e-12
+    np.testing.assert_allclose(res, osvd.residuals(A, Ug, sg, Vg, 10), rtol=1e-6, atol=1e-15)
+    np.testing.assert_allclose(res, ref_res[:10], rtol=1e-2, atol=1e-13)
+    assert res.max() < (1e-12 if p > 1 else 1e-10)
 
 
 def test_randsvd_matches_oracle():
@@ -123,7 +150,7 @@ def test_randsvd_matches_oracle():
     Uo, so, Vo, infos = osvd.randsvd(A, r, p, b, Q0)
     assert info == sum(1 for c in infos if c != 0) == 0
     tol = _weyl(p * 4 + 3, m, sig[0])
-    _compare_triplets(Ug, sg, Vg, Uo, so, Vo, tol, r)
+    _compare_triplets(Ug, sg, Vg, Uo, so, Vo, tol, range(r))
 
 
 def test_lancsvd_tall_paper_shape():
@@ -132,11 +159,15 @@ def test_lancsvd_tall_paper_shape():
     m, n, r, b, p = 100000, 1000, 64, 16, 2
     A, sig = inputs.svd_test_matrix(m, n, seed=9)
     Q1 = inputs.normal_matrix(m, b, seed=10)
-    U, s, V, info = svd.lancsvd(to_dev(A), r, b, p, to_dev(Q1))
-    sg = _h(s)
+    Ad = to_dev(A)
+    U, s, V, info = svd.lancsvd(Ad, r, b, p, to_dev(Q1))
+    Ug, sg, Vg = _h(U), _h(s), _h(V)
     ref = osvd.lancsvd(A, r, p, b, Q1)
     assert info == 0
-    np.testing.assert_allclose(sg, ref["sigma"], rtol=0, atol=_weyl(p * 18 + 2, m, sig[0]))
+    conv, _ = _converged(A, ref)
+    assert len(conv) >= 10
+    _compare_triplets(Ug, sg, Vg, ref["U"], ref["sigma"], ref["V"], _weyl(p * 18 + 2, m, sig[0]), conv)
+    _check_rayleigh_ritz(A, Ug, sg, Vg, r)
     assert np.abs(sg[:10] - sig[:10]).max() < 1e-13 * sig[0]
 
 
