@@ -38,6 +38,7 @@ extern "C" {
 #define CQR_OK 0
 #define CQR_ERR_UNSUPPORTED (-100) /* valid request this build does not support (b > 256, ld > 4e6) */
 #define CQR_ERR_WORKSPACE (-101)   /* work == NULL or work_bytes below the required size     */
+#define CQR_ERR_TOO_LARGE (-102)   /* size above the fixed scratch of cqr_solve_noalloc       */
 #define CQR_ERR_HIP_BASE (-1000)   /* -1000 - hipError_t: a HIP launch or runtime call failed */
 
 /* Precision forms of cqr_factor_mixed. */
@@ -162,6 +163,23 @@ int cqr_solve(int64_t n, const double* Q, int64_t ldq, const double* R, int64_t 
               size_t work_bytes, int32_t* status, void* stream);
 
 /*
+ * cqr_solve for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same results, with the workspace in a fixed array of
+ * 33 MiB that the library holds on each GPU it runs on, from the first call
+ * on that GPU until the process ends.  No allocation, no workspace argument.
+ *   n        0 <= n <= CQR_NOALLOC_MAX_N (65536); above it the call returns
+ *            CQR_ERR_TOO_LARGE and enqueues nothing.
+ *   Q, R, x, status   as for cqr_solve.
+ * All calls on one GPU share that GPU's array, which keeps the last call's
+ * contents; calls that overlap on one GPU (other streams or threads) race and
+ * must not be made.  Asynchronous, kernels only (capturable).
+ */
+#define CQR_NOALLOC_MAX_N 65536
+int cqr_solve_noalloc(int64_t n, const double* Q, int64_t ldq, const double* R, int64_t ldr, double* x,
+                      int32_t* status, void* stream);
+
+/*
  * Low-precision form of cqr_factor (not in the paper, which computes in IEEE
  * double): CGS-QR (Algorithm 3) with the projections H = P^T Q and the updates
  * Q -= P H of Algorithm 5 (S1/S2, S6/S7) on BF16 matrix cores with FP32
@@ -184,6 +202,7 @@ int cqr_solve(int64_t n, const double* Q, int64_t ldq, const double* R, int64_t 
  * Asynchronous and kernels only, like cqr_factor (capturable).
  */
 int cqr_workspace_size_mixed(int64_t q, int64_t r, int64_t b, int prec, size_t* bytes);
+
 int cqr_factor_mixed(int64_t q, int64_t r, int64_t b, int prec, const double* Y, int64_t ldy, float* Q, int64_t ldq,
                      float* R, int64_t ldr, void* work, size_t work_bytes, int32_t* info, int32_t* block_flags,
                      void* stream);

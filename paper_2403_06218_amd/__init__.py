@@ -23,7 +23,7 @@ FLAG_ZERO_COL = 2
 PREC_BF16 = 1
 PREC_FP8 = 2
 
-__all__ = ["colmajor", "workspace_size", "qr", "qr_async", "orth", "orth_against", "solve", "solve_workspace_size",
+__all__ = ["colmajor", "workspace_size", "qr", "qr_async", "orth", "orth_against", "solve", "solve_noalloc", "solve_workspace_size",
            "set_wait_limit_us", "set_forced_breakdown", "qr_mixed", "qr_mixed_async", "solve_ir",
            "synth_uniform",
            "prof_enable", "prof_reset", "prof_query", "prof_names", "CqrError", "version"]
@@ -172,6 +172,22 @@ def solve(Q: torch.Tensor, R: torch.Tensor, rhs: torch.Tensor, work: torch.Tenso
     rc = _native.lib().cqr_solve(n, _ptr(Q), _ld(Q, "Q"), _ptr(R), _ld(R, "R"), _ptr(x), _ptr(work), work.numel(),
                                  _ptr(status), _stream())
     _native.check(rc, "cqr_solve")
+    return x
+
+
+def solve_noalloc(Q: torch.Tensor, R: torch.Tensor, rhs: torch.Tensor, status: torch.Tensor | None = None,
+                  x: torch.Tensor | None = None) -> torch.Tensor:
+    """solve() through the entry point that allocates nothing on the device
+    (its workspace is the library's fixed per-GPU array; n <= 65536).  Only
+    the output x is allocated here, and not even that when x is given."""
+    n = Q.shape[0]
+    if x is None:
+        x = rhs.clone().contiguous()
+    elif x.data_ptr() != rhs.data_ptr():
+        x.copy_(rhs)
+    rc = _native.lib().cqr_solve_noalloc(n, _ptr(Q), _ld(Q, "Q"), _ptr(R), _ld(R, "R"), _ptr(x), _ptr(status),
+                                         _stream())
+    _native.check(rc, "cqr_solve_noalloc")
     return x
 
 

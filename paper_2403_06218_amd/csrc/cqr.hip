@@ -318,6 +318,7 @@ const char* cqr_status_string(int code) {
   if (code == CQR_OK) return "success";
   if (code == CQR_ERR_UNSUPPORTED) return "unsupported parameters (block width must be 1..256, leading dimensions at most 4e6)";
   if (code == CQR_ERR_WORKSPACE) return "workspace missing or too small";
+  if (code == CQR_ERR_TOO_LARGE) return "size above the fixed scratch of the no-allocation entry point (n <= 65536)";
   if (code <= CQR_ERR_HIP_BASE) return hipGetErrorString((hipError_t)(CQR_ERR_HIP_BASE - code));
   if (code < 0 && code > -64) return "invalid argument (the negated return value is its 1-based position)";
   return "unknown status";
