@@ -80,8 +80,18 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(AdjArgs a) {
     if (s > 0) {
       for (int i = wave; i < w; i += NW) {
         const T* rc = R + (size_t)(s + i) * ldr;
+        T rv[kAdjNMax / 64];
+#pragma unroll
+        for (int u = 0; u < kAdjNMax / 64; ++u) {
+          const int p = lane + 64 * u;
+          rv[u] = (p < s) ? rc[p] : T(0);
+        }
         T d = T(0);
-        for (int p = lane; p < s; p += 64) d += rc[p] * sz[p];
+#pragma unroll
+        for (int u = 0; u < kAdjNMax / 64; ++u) {
+          const int p = lane + 64 * u;
+          if (p < s) d += rv[u] * sz[p];
+        }
         d = wsum(d);
         if (lane == 0) sz[s + i] -= d;
       }
@@ -111,14 +121,22 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(AdjArgs a) {
     const int r = tid % kAdjNMax, h = tid / kAdjNMax;
     const int c0 = h ? n / 2 : 0, c1 = h ? n : n / 2;
     if (r < n) {
+      // 16 column loads issued before their products, so that enough loads
+      // are in flight per CU to keep up with its share of HBM bandwidth.
       const T* qr = Q + r;
       T d0 = T(0), d1 = T(0), d2 = T(0), d3 = T(0);
       int c = c0;
-      for (; c + 3 < c1; c += 4) {
-        d0 += qr[(size_t)c * ldq] * sz[c];
-        d1 += qr[(size_t)(c + 1) * ldq] * sz[c + 1];
-        d2 += qr[(size_t)(c + 2) * ldq] * sz[c + 2];
-        d3 += qr[(size_t)(c + 3) * ldq] * sz[c + 3];
+      for (; c + 15 < c1; c += 16) {
+        T qv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) qv[u] = qr[(size_t)(c + u) * ldq];
+#pragma unroll
+        for (int u = 0; u < 16; u += 4) {
+          d0 += qv[u] * sz[c + u];
+          d1 += qv[u + 1] * sz[c + u + 1];
+          d2 += qv[u + 2] * sz[c + u + 2];
+          d3 += qv[u + 3] * sz[c + u + 3];
+        }
       }
       for (; c < c1; ++c) d0 += qr[(size_t)c * ldq] * sz[c];
       const T d = (d0 + d1) + (d2 + d3);
