@@ -3,11 +3,12 @@
 //   lambda = A^{-T} g = Q (R^{-T} g),   dL/dA = -lambda x^T,   dL/db = lambda.
 // One 1024-thread workgroup per matrix: the triangular solve R^T z = g is
 // blocked by 32 (a dot product per column against the finished part of z, one
-// wave per column, then the 32 x 32 triangle in one wave with readlane),
-// lambda = Q z with two threads per row (each half of the columns, four
-// accumulators, then added in a fixed order), and the rank-1 product written
-// column by column (coalesced), the columns split between the two halves.
-// HBM-bound on reading Q and R and writing dA.
+// wave per column, then the 32 x 32 triangle in one wave with readlane);
+// lambda = Q z is accumulated block by block (one thread per row, four
+// accumulators added in a fixed order) by the waves that are idle during each
+// triangle; the rank-1 product is written column by column (coalesced), the
+// columns split between the two halves of the workgroup.  HBM-bound on
+// reading Q and R and writing dA.
 #include "internal.h"
 #include "../../include/cqr.h"
 
@@ -56,7 +57,6 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(AdjArgs a) {
   __shared__ T sz[kAdjNMax];  // g, then z = R^{-T} g
   __shared__ T sx[kAdjNMax];
   __shared__ T sl[kAdjNMax];  // lambda
-  __shared__ T sh[kAdjNMax];  // second half of each row's sum
   const int m = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n = a.n[m];
@@ -74,7 +74,27 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(AdjArgs a) {
     sx[r] = x[r];
   }
   __syncthreads();
-  // R^T z = g, column block by column block.
+  // R^T z = g, column block by column block.  While wave 0 solves the
+  // diagonal triangle of block s, waves 8-15 (one row each) add the previous
+  // block's terms of lambda = Q z, whose z entries are final: the stream
+  // through Q runs under the latency of the substitution.
+  const int lr = tid - kAdjThreads / 2;  // row of lambda owned by waves 8-15
+  const bool lrow = lr >= 0 && lr < n;
+  T l0 = T(0), l1 = T(0), l2 = T(0), l3 = T(0);
+  auto lambda_block = [&](int c0, int c1) {  // columns c0 .. c1-1, c1 - c0 <= 32
+    if (!lrow) return;
+    const T* qr = Q + lr;
+    T qv[32];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) qv[u] = (c0 + u < c1) ? qr[(size_t)(c0 + u) * ldq] : T(0);
+#pragma unroll
+    for (int u = 0; u < 32; u += 4) {
+      if (c0 + u < c1) l0 += qv[u] * sz[c0 + u];
+      if (c0 + u + 1 < c1) l1 += qv[u + 1] * sz[c0 + u + 1];
+      if (c0 + u + 2 < c1) l2 += qv[u + 2] * sz[c0 + u + 2];
+      if (c0 + u + 3 < c1) l3 += qv[u + 3] * sz[c0 + u + 3];
+    }
+  };
   for (int s = 0; s < n; s += 32) {
     const int w = min(32, n - s);
     if (s > 0) {
@@ -113,41 +133,17 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_kernel(AdjArgs a) {
         }
       }
       if (lane < w) sz[s + lane] = gj;
+    } else if (s > 0) {
+      lambda_block(s - 32, s);
     }
     __syncthreads();
   }
-  // lambda = Q z; db = lambda.  Thread (r, h) sums columns [h n/2, (h+1) n/2).
-  {
-    const int r = tid % kAdjNMax, h = tid / kAdjNMax;
-    const int c0 = h ? n / 2 : 0, c1 = h ? n : n / 2;
-    if (r < n) {
-      // 16 column loads issued before their products, so that enough loads
-      // are in flight per CU to keep up with its share of HBM bandwidth.
-      const T* qr = Q + r;
-      T d0 = T(0), d1 = T(0), d2 = T(0), d3 = T(0);
-      int c = c0;
-      for (; c + 15 < c1; c += 16) {
-        T qv[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) qv[u] = qr[(size_t)(c + u) * ldq];
-#pragma unroll
-        for (int u = 0; u < 16; u += 4) {
-          d0 += qv[u] * sz[c + u];
-          d1 += qv[u + 1] * sz[c + u + 1];
-          d2 += qv[u + 2] * sz[c + u + 2];
-          d3 += qv[u + 3] * sz[c + u + 3];
-        }
-      }
-      for (; c < c1; ++c) d0 += qr[(size_t)c * ldq] * sz[c];
-      const T d = (d0 + d1) + (d2 + d3);
-      if (h) sh[r] = d; else sl[r] = d;
-    }
-    __syncthreads();
-    if (h == 0 && r < n) {
-      const T lam = sl[r] + sh[r];
-      sl[r] = lam;
-      db[r] = lam;
-    }
+  // The last block's terms; db = lambda.
+  lambda_block(((n - 1) / 32) * 32, n);
+  if (lrow) {
+    const T lam = (l0 + l1) + (l2 + l3);
+    sl[lr] = lam;
+    db[lr] = lam;
   }
   __syncthreads();
   // dA = -lambda x^T: thread (r, h) writes row r of the columns c = h mod 2.
