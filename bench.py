@@ -47,6 +47,7 @@ def parse():
     p.add_argument("--cpu-target-s", type=float, default=15.0, help="target oracle time for the CPU sample")
     p.add_argument("--no-mixed", action="store_true", help="skip the BF16 + FP64-refinement form")
     p.add_argument("--mixed-b", type=int, default=256, help="block width of the BF16 form")
+    p.add_argument("--no-tiled", action="store_true", help="low-precision forms: column-major finished columns")
     p.add_argument("--no-batched", action="store_true", help="skip the batched form (10,000 uneven sizes)")
     p.add_argument("--no-adjoint", action="store_true", help="skip the adjoint form (256 x n=512)")
     p.add_argument("--no-tune", action="store_true", help="batched form: keep the library's default plan")
@@ -55,6 +56,9 @@ def parse():
     p.add_argument("--svd-m", default="100000,1000000", help="row counts m of the truncated-SVD benchmark")
     p.add_argument("--svd-p", default="1,4", help="restart cycles p of the truncated-SVD benchmark")
     p.add_argument("--no-fp64", action="store_true", help="profiling aid: skip the FP64 n x n measurement")
+    p.add_argument("--counters-only", action="store_true",
+                   help="profiler driver: one untimed FP64 step (--b) and, unless --no-mixed, one BF16 and one FP8 "
+                        "factorisation of the diagonally dominant matrix; no checks, no JSON line")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="before the run, copy this many MiB device-to-device once (reference kernel for HBM counters)")
     return p.parse_args()
@@ -647,6 +651,35 @@ def summary(out: dict) -> dict:
     return s
 
 
+def counters_only(args, torch, cqr):
+    """One step of each form with nothing else around it, for hardware
+    counter passes (rocprofv3 --pmc), which need few launches per run."""
+    n, b = args.n, (args.b if args.b > 0 else 128)
+    dev = torch.device("cuda:0")
+    if args.calib_copy_mib > 0:
+        src = torch.ones(args.calib_copy_mib << 17, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    Y = cqr.colmajor(n, n, device=dev)
+    rhs = torch.empty(n, dtype=torch.float64, device=dev)
+    cqr.synth_uniform(rhs.view(n, 1), args.seed + 1)
+    if not args.no_fp64:
+        cqr.synth_uniform(Y, args.seed)
+        Q, R, info, _ = cqr.qr_async(Y, b)
+        cqr.solve(Q, R, rhs)
+        torch.cuda.synchronize()
+        del R
+        print("counters-only: fp64 n=%d b=%d info=%d" % (n, b, int(info[0])), flush=True)
+    if not args.no_mixed:
+        _fill_c3(cqr, torch, Y, args.seed + 17)
+        for prec in (cqr.PREC_BF16, cqr.PREC_FP8):
+            _, _, info, _ = cqr.qr_mixed_async(Y, args.mixed_b, prec=prec)
+            torch.cuda.synchronize()
+            print("counters-only: prec=%d n=%d b=%d info=%d" % (prec, n, args.mixed_b, int(info[0])), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -660,6 +693,11 @@ def main():
 
     n, K, W = args.n, args.steps, args.warmup
     torch.cuda.set_device(torch.device("cuda:0"))
+    if args.counters_only:
+        counters_only(args, torch, cqr)
+        return
+    if args.no_tiled:
+        cqr.set_mixed_layout(False)
     if args.no_fp64:
         b = args.b if args.b > 0 else 128
         out = {"metric": METRIC, "value": None, "unit": "GFLOP/s", "n_gpus": 1, "steps": K, "warmup": W,

@@ -203,6 +203,15 @@ int cqr_solve_noalloc(int64_t n, const double* Q, int64_t ldq, const double* R, 
  */
 int cqr_workspace_size_mixed(int64_t q, int64_t r, int64_t b, int prec, size_t* bytes);
 
+/*
+ * Testing aid for cqr_factor_mixed: the storage of the finished columns in
+ * the low precision, tiled (1, the default: 128-column blocks of contiguous
+ * 128-byte k-stages, so that every stage of a product reads one contiguous
+ * tile) or column-major (0).  Only where the products read their operand
+ * changes, so the results are the same bits.  Returns -1 for tiled not 0/1.
+ * Process-wide; applies to calls made after it.
+ */
+int cqr_set_mixed_layout(int tiled);
 int cqr_factor_mixed(int64_t q, int64_t r, int64_t b, int prec, const double* Y, int64_t ldy, float* Q, int64_t ldq,
                      float* R, int64_t ldr, void* work, size_t work_bytes, int32_t* info, int32_t* block_flags,
                      void* stream);

@@ -24,7 +24,7 @@ PREC_BF16 = 1
 PREC_FP8 = 2
 
 __all__ = ["colmajor", "workspace_size", "qr", "qr_async", "orth", "orth_against", "solve", "solve_noalloc", "solve_workspace_size",
-           "set_wait_limit_us", "set_forced_breakdown", "qr_mixed", "qr_mixed_async", "solve_ir",
+           "set_wait_limit_us", "set_forced_breakdown", "set_mixed_layout", "qr_mixed", "qr_mixed_async", "solve_ir",
            "synth_uniform",
            "prof_enable", "prof_reset", "prof_query", "prof_names", "CqrError", "version"]
 
@@ -222,6 +222,12 @@ def qr_mixed(Y: torch.Tensor, b: int, prec: int = PREC_BF16, Q: torch.Tensor | N
     stream).  Returns (Q (FP32), R (FP32), info)."""
     Q, R, info, _ = qr_mixed_async(Y, b, prec, Q, R, work)
     return Q, R, int(info[0].item())
+
+
+def set_mixed_layout(tiled: bool = True) -> None:
+    """Testing aid: tiled (default) or column-major storage of the finished
+    low-precision columns of the mixed factorisation (same results)."""
+    _native.check(_native.lib().cqr_set_mixed_layout(1 if tiled else 0), "cqr_set_mixed_layout")
 
 
 def set_forced_breakdown(blk: int) -> None:

@@ -30,6 +30,7 @@ CQR_SIGNATURES = {
     "cqr_solve": ([i64, vp, i64, vp, i64, vp, vp, ctypes.c_size_t, vp, vp], ctypes.c_int),
     "cqr_solve_noalloc": ([i64, vp, i64, vp, i64, vp, vp, vp], ctypes.c_int),
     "cqr_workspace_size_mixed": ([i64, i64, i64, ctypes.c_int, szp], ctypes.c_int),
+    "cqr_set_mixed_layout": ([ctypes.c_int], ctypes.c_int),
     "cqr_factor_mixed": ([i64, i64, i64, ctypes.c_int, vp, i64, vp, i64, vp, i64, vp, ctypes.c_size_t, vp, vp, vp],
                          ctypes.c_int),
     "cqr_solve_ir_workspace_size": ([i64, szp], ctypes.c_int),

@@ -221,21 +221,17 @@ __global__ void __launch_bounds__(kFbThreads) cgs2_fallback_kernel(FbArgs<TP> a)
   }
 }
 
-int g_fb_grid = 0;  // resident workgroups of the fallback kernel (all CUs), found once
+int g_fb_grid = 0;  // workgroups of the fallback kernel: one per CU, found once
 
+// One 256-thread workgroup per CU, with a few hundred bytes of LDS and no
+// register pressure, is always resident at once on an idle device, so the
+// grid barriers never wait for a workgroup that cannot start.
 int fb_max_grid() {
   if (g_fb_grid > 0) return g_fb_grid;
-  int dev = 0, cus = 0, per64 = 0, per32 = 0;
+  int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per64, (const void*)cgs2_fallback_kernel<double>, kFbThreads, 0) !=
-      hipSuccess)
-    return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per32, (const void*)cgs2_fallback_kernel<float>, kFbThreads, 0) !=
-      hipSuccess)
-    return 0;
-  if (per64 < 1 || per32 < 1) return 0;
-  g_fb_grid = cus;  // one workgroup per CU: every workgroup is resident at once
+  g_fb_grid = cus;
   return g_fb_grid;
 }
 

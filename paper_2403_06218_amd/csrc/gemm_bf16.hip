@@ -226,7 +226,7 @@ gemm_bf16_kernel(int64_t M, int64_t N, int64_t K, float alpha, const __bf16* __r
 // power-of-two scales of the FP8 operands.
 template <typename E, int ROLE, int OUT, int SA = 6, int SB = 2, int MT_ = 128>
 __global__ void __launch_bounds__(512, 1)
-gemm_lp_wide_kernel(int64_t M, int64_t N, int64_t K, float alpha, const E* __restrict__ A, int64_t lda,
+gemm_lp_wide_kernel(int64_t M, int64_t N, int64_t K, float alpha, const E* __restrict__ A, int64_t lda, int64_t a_blk,
                     const E* __restrict__ B, int64_t ldb, float beta, void* C, int64_t ldc, int64_t kchunk,
                     float* __restrict__ part, const float* __restrict__ rs, const float* __restrict__ cs,
                     const int* __restrict__ gate) {
@@ -285,17 +285,20 @@ gemm_lp_wide_kernel(int64_t M, int64_t N, int64_t K, float alpha, const E* __res
     const int x = p / 8, c = (p % 8) ^ ((x >> 1) & 7);
     if (aloader) {
       const int64_t m = (m0 + x < M) ? m0 + x : M - 1;
-      off[t] = EPC * c + m * lda;
+      off[t] = EPC * c + (a_blk ? (m >> 7) * a_blk + (m & 127) * KST : m * lda);
     } else {
       const int64_t n = (n0 + x < N) ? n0 + x : N - 1;
       off[t] = EPC * c + n * ldb;
     }
   }
+  // A tiled (a_blk > 0): stage k0 of a 128-column block is one contiguous
+  // 128 x KST tile, so the stage origin moves by 128 KST per stage.
+  const int64_t kmul = a_blk ? 128 : 1;
   auto issueA = [&](int st, auto slot) {
     const int64_t k0 = kbeg + (int64_t)st * KST;
     char* la = slotA(slot);
 #pragma unroll
-    for (int t = 0; t < AINS; ++t) dma16_stream(A + k0 + off[t], la + (lw * AINS + t) * 1024);
+    for (int t = 0; t < AINS; ++t) dma16_stream(A + k0 * kmul + off[t], la + (lw * AINS + t) * 1024);
   };
   auto issueB = [&](int st, auto slot) {
     const int64_t k0 = kbeg + (int64_t)st * KST;
@@ -485,21 +488,23 @@ hipError_t launch_bf16(int64_t M, int64_t N, int64_t K, float alpha, const __bf1
 
 template <int ROLE, int OUT>
 hipError_t launch_bf16_tile(int64_t M, int64_t N, int64_t K, float alpha, const __bf16* A, int64_t lda,
-                            const __bf16* B, int64_t ldb, float beta, void* C, int64_t ldc, int64_t kchunk, int nsplit,
-                            float* part, const int* gate, hipStream_t s) {
-  if (M > 64 && N > 128) {
+                            int64_t a_blk, const __bf16* B, int64_t ldb, float beta, void* C, int64_t ldc,
+                            int64_t kchunk, int nsplit, float* part, const int* gate, hipStream_t s) {
+  // A tiled A is read by the wide kernel only (columns past M or N are
+  // clamped and not stored, so any shape fits it).
+  if ((M > 64 && N > 128) || a_blk > 0) {
     if constexpr (ROLE == ROLE_PROJ) {
       if (wide_mt(ROLE, M) == 256) {
         const dim3 grid((unsigned)((M + 255) / 256), (unsigned)((N + 255) / 256), (unsigned)nsplit);
         hipLaunchKernelGGL((gemm_lp_wide_kernel<__bf16, ROLE, OUT, 3, 2, 256>), grid, dim3(512), 0, s, M, N, K, alpha,
-                           A, lda, B, ldb, beta, C, ldc, kchunk, part, (const float*)nullptr, (const float*)nullptr,
+                           A, lda, a_blk, B, ldb, beta, C, ldc, kchunk, part, (const float*)nullptr, (const float*)nullptr,
                            gate);
         return hipGetLastError();
       }
     }
     const dim3 grid((unsigned)((M + 127) / 128), (unsigned)((N + 255) / 256), (unsigned)nsplit);
-    hipLaunchKernelGGL((gemm_lp_wide_kernel<__bf16, ROLE, OUT>), grid, dim3(512), 0, s, M, N, K, alpha, A, lda, B,
-                       ldb, beta, C, ldc, kchunk, part, (const float*)nullptr, (const float*)nullptr, gate);
+    hipLaunchKernelGGL((gemm_lp_wide_kernel<__bf16, ROLE, OUT>), grid, dim3(512), 0, s, M, N, K, alpha, A, lda, a_blk,
+                       B, ldb, beta, C, ldc, kchunk, part, (const float*)nullptr, (const float*)nullptr, gate);
     return hipGetLastError();
   }
   if (M > 64 && N > 64)
@@ -514,8 +519,8 @@ hipError_t launch_bf16_tile(int64_t M, int64_t N, int64_t K, float alpha, const 
   return launch_bf16<ROLE, OUT, 64, 64>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, nsplit, part, gate, s);
 }
 
-int64_t bf16_tiles(int role, int64_t M, int64_t N) {
-  const bool wide = M > 64 && N > 128;
+int64_t bf16_tiles(int role, int64_t M, int64_t N, bool force_wide) {
+  const bool wide = (M > 64 && N > 128) || force_wide;
   const int64_t mt = wide ? wide_mt(role, M) : (M > 64 ? 128 : 64), nt = wide ? 256 : (N > 64 ? 128 : 64);
   return ((M + mt - 1) / mt) * ((N + nt - 1) / nt);
 }
@@ -528,15 +533,16 @@ bool gemm_bf16_supported(const void* A, int64_t lda, const void* B, int64_t ldb,
 }
 
 hipError_t gemm_bf16_tn(Role role, int64_t M, int64_t N, int64_t K, float alpha, const __bf16* A, int64_t lda,
-                        const __bf16* B, int64_t ldb, float beta, void* C, int64_t ldc, bool c_is_f64, float* part,
-                        size_t part_cap, const int* gate, hipStream_t s, double flops) {
+                        int64_t a_blk, const __bf16* B, int64_t ldb, float beta, void* C, int64_t ldc, bool c_is_f64,
+                        float* part, size_t part_cap, const int* gate, hipStream_t s, double flops) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  if (!gemm_bf16_supported(A, lda, B, ldb, K)) return hipErrorInvalidValue;
+  if (!gemm_bf16_supported(A, a_blk ? 8 : lda, B, ldb, K)) return hipErrorInvalidValue;
+  if (a_blk < 0 || a_blk % (128 * kBKT) != 0) return hipErrorInvalidValue;
   // Split-K through FP32 partial sums: fill whole rounds of 256 resident
   // workgroups, each walking at least 4 stages, within the partial buffer.
   int nsplit = 1;
   if (part != nullptr) {
-    const int64_t tiles = bf16_tiles(role, M, N);
+    const int64_t tiles = bf16_tiles(role, M, N, a_blk > 0);
     int64_t max_split = K / (4 * kBKT);
     const int64_t by_cap = (int64_t)(part_cap / (size_t)(M * N));
     if (max_split > by_cap) max_split = by_cap;
@@ -564,18 +570,18 @@ hipError_t gemm_bf16_tn(Role role, int64_t M, int64_t N, int64_t K, float alpha,
   hipError_t e;
   if (nsplit > 1)
     e = (role == ROLE_UPDATE)
-            ? launch_bf16_tile<ROLE_UPDATE, 0>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, nsplit, part,
+            ? launch_bf16_tile<ROLE_UPDATE, 0>(M, N, K, alpha, A, lda, a_blk, B, ldb, beta, C, ldc, kchunk, nsplit, part,
                                                gate, s)
-            : launch_bf16_tile<ROLE_PROJ, 0>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, nsplit, part, gate,
+            : launch_bf16_tile<ROLE_PROJ, 0>(M, N, K, alpha, A, lda, a_blk, B, ldb, beta, C, ldc, kchunk, nsplit, part, gate,
                                              s);
   else if (c_is_f64)
     e = (role == ROLE_UPDATE)
-            ? launch_bf16_tile<ROLE_UPDATE, 2>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, 1, part, gate, s)
-            : launch_bf16_tile<ROLE_PROJ, 2>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, 1, part, gate, s);
+            ? launch_bf16_tile<ROLE_UPDATE, 2>(M, N, K, alpha, A, lda, a_blk, B, ldb, beta, C, ldc, kchunk, 1, part, gate, s)
+            : launch_bf16_tile<ROLE_PROJ, 2>(M, N, K, alpha, A, lda, a_blk, B, ldb, beta, C, ldc, kchunk, 1, part, gate, s);
   else
     e = (role == ROLE_UPDATE)
-            ? launch_bf16_tile<ROLE_UPDATE, 1>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, 1, part, gate, s)
-            : launch_bf16_tile<ROLE_PROJ, 1>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, 1, part, gate, s);
+            ? launch_bf16_tile<ROLE_UPDATE, 1>(M, N, K, alpha, A, lda, a_blk, B, ldb, beta, C, ldc, kchunk, 1, part, gate, s)
+            : launch_bf16_tile<ROLE_PROJ, 1>(M, N, K, alpha, A, lda, a_blk, B, ldb, beta, C, ldc, kchunk, 1, part, gate, s);
   prof_end(slot, role, s, flops, bytes);
   if (e != hipSuccess || nsplit == 1) return e;
   const int64_t total = M * N;
@@ -599,10 +605,12 @@ bool gemm_fp8_supported(const void* A, int64_t lda, const void* B, int64_t ldb, 
 }
 
 hipError_t gemm_fp8_tn(Role role, int64_t M, int64_t N, int64_t K, float alpha, const uint8_t* A, int64_t lda,
-                       const uint8_t* B, int64_t ldb, float beta, void* C, int64_t ldc, bool c_is_f64, const float* rs,
-                       const float* cs, float* part, size_t part_cap, const int* gate, hipStream_t s, double flops) {
+                       int64_t a_blk, const uint8_t* B, int64_t ldb, float beta, void* C, int64_t ldc, bool c_is_f64,
+                       const float* rs, const float* cs, float* part, size_t part_cap, const int* gate, hipStream_t s,
+                       double flops) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  if (!gemm_fp8_supported(A, lda, B, ldb, K)) return hipErrorInvalidValue;
+  if (!gemm_fp8_supported(A, a_blk ? 16 : lda, B, ldb, K)) return hipErrorInvalidValue;
+  if (a_blk < 0 || a_blk % (128 * 128) != 0) return hipErrorInvalidValue;
   // The wide tile (columns past N are clamped and not stored), 128 or 256 rows.
   const int mt = wide_mt(role, M);
   int nsplit = 1;
@@ -638,25 +646,25 @@ hipError_t gemm_fp8_tn(Role role, int64_t M, int64_t N, int64_t K, float alpha, 
   if (mt == 256) {
     if (nsplit > 1)
       hipLaunchKernelGGL((gemm_lp_wide_kernel<fp8_t, ROLE_PROJ, 0, 3, 2, 256>), grid, dim3(512), 0, s, M, N, K, alpha,
-                         a8, lda, b8, ldb, beta, C, ldc, kchunk, part, rs, cs, gate);
+                         a8, lda, a_blk, b8, ldb, beta, C, ldc, kchunk, part, rs, cs, gate);
     else if (c_is_f64)
       hipLaunchKernelGGL((gemm_lp_wide_kernel<fp8_t, ROLE_PROJ, 2, 3, 2, 256>), grid, dim3(512), 0, s, M, N, K, alpha,
-                         a8, lda, b8, ldb, beta, C, ldc, kchunk, part, rs, cs, gate);
+                         a8, lda, a_blk, b8, ldb, beta, C, ldc, kchunk, part, rs, cs, gate);
     else
       return hipErrorInvalidValue;
   } else if (nsplit > 1) {
     if (role == ROLE_UPDATE)
-      hipLaunchKernelGGL((gemm_lp_wide_kernel<fp8_t, ROLE_UPDATE, 0>), grid, dim3(512), 0, s, M, N, K, alpha, a8, lda,
+      hipLaunchKernelGGL((gemm_lp_wide_kernel<fp8_t, ROLE_UPDATE, 0>), grid, dim3(512), 0, s, M, N, K, alpha, a8, lda, a_blk,
                          b8, ldb, beta, C, ldc, kchunk, part, rs, cs, gate);
     else
-      hipLaunchKernelGGL((gemm_lp_wide_kernel<fp8_t, ROLE_PROJ, 0>), grid, dim3(512), 0, s, M, N, K, alpha, a8, lda,
+      hipLaunchKernelGGL((gemm_lp_wide_kernel<fp8_t, ROLE_PROJ, 0>), grid, dim3(512), 0, s, M, N, K, alpha, a8, lda, a_blk,
                          b8, ldb, beta, C, ldc, kchunk, part, rs, cs, gate);
   } else if (c_is_f64) {
     if (role == ROLE_UPDATE)
-      hipLaunchKernelGGL((gemm_lp_wide_kernel<fp8_t, ROLE_UPDATE, 2>), grid, dim3(512), 0, s, M, N, K, alpha, a8, lda,
+      hipLaunchKernelGGL((gemm_lp_wide_kernel<fp8_t, ROLE_UPDATE, 2>), grid, dim3(512), 0, s, M, N, K, alpha, a8, lda, a_blk,
                          b8, ldb, beta, C, ldc, kchunk, part, rs, cs, gate);
     else
-      hipLaunchKernelGGL((gemm_lp_wide_kernel<fp8_t, ROLE_PROJ, 2>), grid, dim3(512), 0, s, M, N, K, alpha, a8, lda,
+      hipLaunchKernelGGL((gemm_lp_wide_kernel<fp8_t, ROLE_PROJ, 2>), grid, dim3(512), 0, s, M, N, K, alpha, a8, lda, a_blk,
                          b8, ldb, beta, C, ldc, kchunk, part, rs, cs, gate);
   } else {
     return hipErrorInvalidValue;

@@ -55,10 +55,14 @@ hipError_t gemm_nn(Role role, int64_t M, int64_t N, int64_t K, double alpha, con
 // A (K x M) and B (K x N) BF16, k-contiguous.  C is FP64 when c_is_f64, else
 // FP32 (then split over K through `part`, capacity part_cap floats).
 // Requires 16-byte aligned A and B, lda and ldb multiples of 8, K a multiple of 64.
+// A is column-major (lda) when a_blk == 0, else tiled: columns in blocks of
+// 128, each block a_blk elements holding its k-stages (64 k, 128 bytes per
+// column) one after the other, each stage 128 columns x 64 k contiguous:
+// element (k, m) at (m / 128) a_blk + (k / 64) 8192 + (m % 128) 64 + k % 64.
 bool gemm_bf16_supported(const void* A, int64_t lda, const void* B, int64_t ldb, int64_t K);
 hipError_t gemm_bf16_tn(Role role, int64_t M, int64_t N, int64_t K, float alpha, const __bf16* A, int64_t lda,
-                        const __bf16* B, int64_t ldb, float beta, void* C, int64_t ldc, bool c_is_f64, float* part,
-                        size_t part_cap, const int* gate, hipStream_t s, double flops);
+                        int64_t a_blk, const __bf16* B, int64_t ldb, float beta, void* C, int64_t ldc, bool c_is_f64,
+                        float* part, size_t part_cap, const int* gate, hipStream_t s, double flops);
 
 // FP8 (OCP E4M3 bytes) GEMM with FP32 accumulation, same contract as
 // gemm_bf16_tn (C FP64 only, or FP32 split-K partials reduced into FP64 C),
@@ -66,9 +70,12 @@ hipError_t gemm_bf16_tn(Role role, int64_t M, int64_t N, int64_t K, float alpha,
 // inverse power-of-two scales of the operands).  Requires 16-byte aligned A
 // and B, lda and ldb multiples of 16, K a multiple of 128.
 bool gemm_fp8_supported(const void* A, int64_t lda, const void* B, int64_t ldb, int64_t K);
+// A tiled as for BF16 with 128-k stages (128 bytes per column): element
+// (k, m) at (m / 128) a_blk + (k / 128) 16384 + (m % 128) 128 + k % 128.
 hipError_t gemm_fp8_tn(Role role, int64_t M, int64_t N, int64_t K, float alpha, const uint8_t* A, int64_t lda,
-                       const uint8_t* B, int64_t ldb, float beta, void* C, int64_t ldc, bool c_is_f64, const float* rs,
-                       const float* cs, float* part, size_t part_cap, const int* gate, hipStream_t s, double flops);
+                       int64_t a_blk, const uint8_t* B, int64_t ldb, float beta, void* C, int64_t ldc, bool c_is_f64,
+                       const float* rs, const float* cs, float* part, size_t part_cap, const int* gate, hipStream_t s,
+                       double flops);
 
 // Lower Cholesky W = L L^T of a b x b SPD matrix (b <= 128) and the inverse of
 // L, in one workgroup.  Writes LT = L^T and XT = (L^{-1})^T (both b x b,

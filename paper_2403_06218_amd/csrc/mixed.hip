@@ -26,34 +26,57 @@ namespace {
     if (e_ != hipSuccess) return CQR_ERR_HIP_BASE - (int)e_;  \
   } while (0)
 
+#define MX_RC(expr)             \
+  do {                          \
+    const int rc_ = (expr);     \
+    if (rc_ != CQR_OK) return rc_; \
+  } while (0)
+
 size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 int64_t up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+bool g_tiled = true;  // tiled storage of the finished columns (cqr_set_mixed_layout)
+
+// Element (k, m) of a tiled K x M operand with 128-column blocks of a_blk
+// elements and k-stages of kst elements (128 bytes per column).
+__device__ __forceinline__ int64_t tiled_index(int64_t k, int64_t m, int64_t a_blk, int kst) {
+  return (m >> 7) * a_blk + (k / kst) * (128 * (int64_t)kst) + (m & 127) * kst + (k % kst);
+}
+
+// Buffers of the column block being orthogonalised.
+struct Slot {
+  double* Qj;       // q x b working block (FP64)
+  double* H;        // rp x b first-pass projection (FP64)
+  __bf16* B16;      // qp x b: BF16 copy of the block being projected (ld qp)
+  __bf16* H16;      // rp x b: BF16 copy of a projection (ld rp)
+  uint8_t* B8;      // qp x b: FP8 copy of the block
+  uint8_t* H8;      // rp x b: FP8 copy of a projection
+  float* binv;      // b: inverse scales of the block's columns (FP8)
+};
 
 struct MixedWork {
   int* status;
   double *W, *LT1, *XT1, *LT2, *XT2, *Rjj;  // b x b
-  double* Qj;       // q x b working block (FP64)
   double* T;        // q x b after the first pass
-  double* H;        // r x b projections, first pass (FP64)
-  double* Hb;       // r x b projections, second pass
+  double* Hb;       // rp x b projections, second pass
+  Slot slot;
   // BF16 form
   __bf16* P16;      // qp x rp: finished columns, column-major (ld qp)
   __bf16* P16T;     // rp x qp: finished columns transposed (ld rp)
-  __bf16* B16;      // qp x b: BF16 copy of the block being projected (ld qp)
-  __bf16* H16;      // rp x b: BF16 copy of a projection (ld rp)
   // FP8 form (OCP E4M3 bytes, each column with a power-of-two scale)
   uint8_t* P8;      // qp x rp
   uint8_t* P8T;     // rp x qp
-  uint8_t* B8;      // qp x b
-  uint8_t* H8;      // rp x b
   float* pinv;      // rp: inverse scale of each finished column
-  float* binv;      // b: inverse scales of the block's columns
-  float* hinv;      // b: inverse scales of a projection's columns
+  float* hinv;      // b: inverse scales of a projection's columns (FP8)
   double* cmax;     // b: column maxima
   float* part;      // split-K partial sums
   size_t part_cap;
   void* fb;         // breakdown fallback workspace (counters first; zero at the start of a call)
   int64_t qp, rp;
+  // Tiled storage of the finished columns (see gemm_bf16_tn): a_blk of P
+  // (K = qp rows, 128-column blocks) and of P^T (K = rp, 128-row blocks);
+  // 0 = column-major.
+  int64_t blk_p, blk_pt;
 };
 
 size_t mixed_layout(int64_t q, int64_t r, int64_t b, int prec, char* base, MixedWork* w) {
@@ -66,9 +89,13 @@ size_t mixed_layout(int64_t q, int64_t r, int64_t b, int prec, char* base, Mixed
   MixedWork tmp;
   MixedWork* o = w ? w : &tmp;
   memset(o, 0, sizeof(*o));
-  const int64_t pad = (prec == CQR_PREC_FP8) ? 128 : 64;
-  o->qp = up(q > 0 ? q : 1, pad);
-  o->rp = up(r > 0 ? r : 1, pad);
+  // Rows and columns of the low-precision copies padded to 128 (the tiled
+  // layout's column blocks; a multiple of the BF16 and FP8 k-stages).
+  o->qp = up(q > 0 ? q : 1, 128);
+  o->rp = up(r > 0 ? r : 1, 128);
+  const bool tiled = g_tiled;
+  o->blk_p = tiled ? o->qp * 128 : 0;
+  o->blk_pt = tiled ? o->rp * 128 : 0;
   const size_t bb = (size_t)b * b * 8, qb = (size_t)q * b * 8;
   o->status = (int*)take(64);
   o->W = (double*)take(bb);
@@ -77,25 +104,31 @@ size_t mixed_layout(int64_t q, int64_t r, int64_t b, int prec, char* base, Mixed
   o->LT2 = (double*)take(bb);
   o->XT2 = (double*)take(bb);
   o->Rjj = (double*)take(bb);
-  o->Qj = (double*)take(qb);
   o->T = (double*)take(qb);
-  o->H = (double*)take((size_t)o->rp * b * 8);
   o->Hb = (double*)take((size_t)o->rp * b * 8);
+  {
+    Slot& sl = o->slot;
+    sl.Qj = (double*)take(qb);
+    sl.H = (double*)take((size_t)o->rp * b * 8);
+    if (prec == CQR_PREC_FP8) {
+      sl.B8 = (uint8_t*)take((size_t)o->qp * b);
+      sl.H8 = (uint8_t*)take((size_t)o->rp * b);
+      sl.binv = (float*)take((size_t)b * 4);
+    } else {
+      sl.B16 = (__bf16*)take((size_t)o->qp * b * 2);
+      sl.H16 = (__bf16*)take((size_t)o->rp * b * 2);
+    }
+  }
   if (prec == CQR_PREC_FP8) {
     o->P8 = (uint8_t*)take((size_t)o->qp * o->rp);
     o->P8T = (uint8_t*)take((size_t)o->rp * o->qp);
-    o->B8 = (uint8_t*)take((size_t)o->qp * b);
-    o->H8 = (uint8_t*)take((size_t)o->rp * b);
     o->pinv = (float*)take((size_t)o->rp * 4);
-    o->binv = (float*)take((size_t)b * 4);
     o->hinv = (float*)take((size_t)b * 4);
-    o->cmax = (double*)take((size_t)b * 8);
   } else {
     o->P16 = (__bf16*)take((size_t)o->qp * o->rp * 2);
     o->P16T = (__bf16*)take((size_t)o->rp * o->qp * 2);
-    o->B16 = (__bf16*)take((size_t)o->qp * b * 2);
-    o->H16 = (__bf16*)take((size_t)o->rp * b * 2);
   }
+  o->cmax = (double*)take((size_t)b * 8);
   o->part_cap = (size_t)16 << 20;
   o->part = (float*)take(o->part_cap * 4);
   o->fb = take(fallback_workspace_bytes(r > b ? r : b));
@@ -205,8 +238,8 @@ to_fp8_kernel(int64_t rows, int64_t rows_pad, int64_t cols, const double* __rest
 __global__ void __launch_bounds__(256)
 finish_block_fp8_kernel(int64_t q, int w, const double* __restrict__ Qj, int64_t ldj, float* __restrict__ Q32,
                         int64_t ldq, uint8_t* __restrict__ P8, int64_t ldp, uint8_t* __restrict__ P8T, int64_t ldpt,
-                        const double* __restrict__ cmax, float* __restrict__ pinv, int64_t c0,
-                        const int* __restrict__ gate) {
+                        int64_t blk_p, int64_t blk_pt, const double* __restrict__ cmax, float* __restrict__ pinv,
+                        int64_t c0, const int* __restrict__ gate) {
   if (gate != nullptr && *gate != 0) return;
   __shared__ uint8_t tile[64][65];
   const int64_t i0 = (int64_t)blockIdx.x * 64;
@@ -220,7 +253,7 @@ finish_block_fp8_kernel(int64_t q, int w, const double* __restrict__ Qj, int64_t
       const float sc = pow2_scale(cmax[j]);
       Q32[i + (c0 + j) * ldq] = (float)v;
       const uint8_t h = to_e4m3((float)(v * (double)sc));
-      P8[i + (c0 + j) * ldp] = h;
+      P8[blk_p ? tiled_index(i, c0 + j, blk_p, 128) : i + (c0 + j) * ldp] = h;
       tile[jj][tx] = h;
       if (i == 0) pinv[c0 + j] = 1.f / sc;
     }
@@ -229,7 +262,7 @@ finish_block_fp8_kernel(int64_t q, int w, const double* __restrict__ Qj, int64_t
   for (int ii = ty; ii < 64; ii += 4) {
     const int64_t i = i0 + ii;
     const int j = j0 + tx;
-    if (i < q && j < w) P8T[(c0 + j) + i * ldpt] = tile[tx][ii];
+    if (i < q && j < w) P8T[blk_pt ? tiled_index(c0 + j, i, blk_pt, 128) : (c0 + j) + i * ldpt] = tile[tx][ii];
   }
 }
 
@@ -239,7 +272,7 @@ finish_block_fp8_kernel(int64_t q, int w, const double* __restrict__ Qj, int64_t
 __global__ void __launch_bounds__(256)
 finish_block_kernel(int64_t q, int w, const double* __restrict__ Qj, int64_t ldj, float* __restrict__ Q32,
                     int64_t ldq, __bf16* __restrict__ P16, int64_t ldp, __bf16* __restrict__ P16T, int64_t ldpt,
-                    int64_t c0, const int* __restrict__ gate) {
+                    int64_t blk_p, int64_t blk_pt, int64_t c0, const int* __restrict__ gate) {
   if (gate != nullptr && *gate != 0) return;
   __shared__ __bf16 tile[64][65];
   const int64_t i0 = (int64_t)blockIdx.x * 64;
@@ -252,7 +285,7 @@ finish_block_kernel(int64_t q, int w, const double* __restrict__ Qj, int64_t ldj
       const double v = Qj[i + (int64_t)j * ldj];
       Q32[i + (c0 + j) * ldq] = (float)v;
       const __bf16 h = (__bf16)v;
-      P16[i + (c0 + j) * ldp] = h;
+      P16[blk_p ? tiled_index(i, c0 + j, blk_p, 64) : i + (c0 + j) * ldp] = h;
       tile[jj][tx] = h;
     }
   }
@@ -260,7 +293,7 @@ finish_block_kernel(int64_t q, int w, const double* __restrict__ Qj, int64_t ldj
   for (int ii = ty; ii < 64; ii += 4) {
     const int64_t i = i0 + ii;
     const int j = j0 + tx;
-    if (i < q && j < w) P16T[(c0 + j) + i * ldpt] = tile[tx][ii];
+    if (i < q && j < w) P16T[blk_pt ? tiled_index(c0 + j, i, blk_pt, 64) : (c0 + j) + i * ldpt] = tile[tx][ii];
   }
 }
 
@@ -409,127 +442,144 @@ __global__ void __launch_bounds__(256) axpy_kernel(int64_t n, const double* __re
 // Breakdown fallback of one block (Section 3): when a Cholesky factorisation
 // of the block broke down (or the block's breakdown is forced), the block is
 // restored from Y and redone column by column by CGS2 in FP64 arithmetic
-// against the FP32 finished columns, writing ws.Qj, the projections ws.H and
-// the triangle ws.Rjj; info and flags record it and the status word is
+// against the FP32 finished columns, writing the slot's Qj, its projections H
+// and the triangle ws.Rjj; info and flags record it and the status word is
 // cleared, so the block's remaining steps run.  An empty launch otherwise.
 hipError_t block_fallback(int64_t q, int64_t w, int64_t s, const double* Yj, int64_t ldy, const float* Q32,
-                          int64_t ldq, const MixedWork& ws, int blk, int32_t* info, int32_t* flags, hipStream_t st) {
+                          int64_t ldq, const MixedWork& ws, const Slot& sl, int blk, int32_t* info, int32_t* flags,
+                          hipStream_t st) {
   if (blk == forced_breakdown_block()) {
     hipError_t e = force_breakdown(ws.status, blk, st);
     if (e != hipSuccess) return e;
   }
-  return cgs2_fallback_f32basis(q, s, w, Q32, ldq, ws.Qj, q, ws.H, ws.rp, ws.Rjj, w, Yj, ldy, ws.status, info, flags,
+  return cgs2_fallback_f32basis(q, s, w, Q32, ldq, sl.Qj, q, sl.H, ws.rp, ws.Rjj, w, Yj, ldy, ws.status, info, flags,
                                 blk, ws.fb, st);
 }
 
-// One column block of the BF16 form (see the file comment).
-int mixed_block(int64_t q, int64_t w, int64_t s, const double* Yj, int64_t ldy, float* Q32, int64_t ldq, float* R32,
-                int64_t ldr, const MixedWork& ws, int blk, int32_t* info, int32_t* flags, hipStream_t st) {
+// The low-precision copy of a block X (q x w, FP64) as the projection's B
+// operand: BF16, or FP8 with its column scales (binv) from the column maxima.
+int stage_operand(int prec, int64_t q, int64_t w, const double* X, const MixedWork& ws, const Slot& sl, double* cmax,
+                  const int* gate, hipStream_t st) {
+  if (prec == CQR_PREC_FP8) {
+    hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)w), dim3(kColmaxThreads), 0, st, q, X, q, (const float*)nullptr,
+                       cmax, gate);
+    MX_TRY(hipGetLastError());
+    hipLaunchKernelGGL(to_fp8_kernel, cvt_grid(ws.qp, w), dim3(256), 0, st, q, ws.qp, w, X, q, (const float*)nullptr,
+                       cmax, sl.B8, ws.qp, sl.binv, gate);
+  } else {
+    hipLaunchKernelGGL(to_bf16_kernel, cvt_grid(ws.qp, w), dim3(256), 0, st, q, ws.qp, w, X, q, sl.B16, ws.qp, gate);
+  }
+  MX_TRY(hipGetLastError());
+  return CQR_OK;
+}
+
+// Classical Gram-Schmidt step of Algorithm 5 (S1/S2 or S6/S7) against the
+// finished columns c0 .. c1-1, from the low-precision copy of X staged in the
+// slot: Hd[c0:c1] = P[:, c0:c1]^T X (FP32 accumulation into FP64), then
+// X -= P[:, c0:c1] Hd[c0:c1] with the projection rounded to the low precision
+// (hinv: its column scales in the FP8 form).  c0 is a multiple of the K
+// granule (64 BF16, 128 FP8); rows c1 .. up(c1) - 1 of the copy are zero.
+int project_update(int prec, int64_t q, int64_t w, int64_t c0, int64_t c1, double* X, double* Hd,
+                   const MixedWork& ws, const Slot& sl, float* hinv, double* cmax, float* part, const int* gate,
+                   hipStream_t st) {
+  const int64_t m = c1 - c0;
+  if (m <= 0) return CQR_OK;
+  const double flops = 2.0 * (double)w * (double)q * (double)m;
+  if (prec == CQR_PREC_FP8) {
+    const int64_t kp = up(c1, 128) - c0;
+    const uint8_t* pa = ws.blk_p ? ws.P8 + (c0 >> 7) * ws.blk_p : ws.P8 + c0 * ws.qp;
+    MX_TRY(gemm_fp8_tn(ROLE_PROJ, m, w, ws.qp, 1.0f, pa, ws.qp, ws.blk_p, sl.B8, ws.qp, 0.0f, Hd + c0, ws.rp, true,
+                       ws.pinv + c0, sl.binv, part, ws.part_cap, gate, st, flops));
+    // H' = diag(1/s_P) H, then per-column scales for its FP8 copy.
+    hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)w), dim3(kColmaxThreads), 0, st, m, Hd + c0, ws.rp,
+                       ws.pinv + c0, cmax, gate);
+    MX_TRY(hipGetLastError());
+    hipLaunchKernelGGL(to_fp8_kernel, cvt_grid(kp, w), dim3(256), 0, st, m, kp, w, Hd + c0, ws.rp, ws.pinv + c0,
+                       cmax, sl.H8 + c0, ws.rp, hinv, gate);
+    MX_TRY(hipGetLastError());
+    // X -= (P diag(s_P)) (diag(1/s_P) H), columns undone by 1/s_H.
+    const uint8_t* pt = ws.blk_pt ? ws.P8T + c0 * 128 : ws.P8T + c0;
+    MX_TRY(gemm_fp8_tn(ROLE_UPDATE, q, w, kp, -1.0f, pt, ws.rp, ws.blk_pt, sl.H8 + c0, ws.rp, 1.0f, X, q, true,
+                       nullptr, hinv, nullptr, 0, gate, st, flops));
+  } else {
+    const int64_t kp = up(c1, 64) - c0;
+    const __bf16* pa = ws.blk_p ? ws.P16 + (c0 >> 7) * ws.blk_p : ws.P16 + c0 * ws.qp;
+    MX_TRY(gemm_bf16_tn(ROLE_PROJ, m, w, ws.qp, 1.0f, pa, ws.qp, ws.blk_p, sl.B16, ws.qp, 0.0f, Hd + c0, ws.rp, true,
+                        part, ws.part_cap, gate, st, flops));
+    hipLaunchKernelGGL(to_bf16_kernel, cvt_grid(kp, w), dim3(256), 0, st, m, kp, w, Hd + c0, ws.rp, sl.H16 + c0,
+                       ws.rp, gate);
+    MX_TRY(hipGetLastError());
+    // X -= P H  (A = P^T stored k-contiguous)
+    const __bf16* pt = ws.blk_pt ? ws.P16T + c0 * 128 : ws.P16T + c0;
+    MX_TRY(gemm_bf16_tn(ROLE_UPDATE, q, w, kp, -1.0f, pt, ws.rp, ws.blk_pt, sl.H16 + c0, ws.rp, 1.0f, X, q, true,
+                        nullptr, 0, gate, st, flops));
+  }
+  return CQR_OK;
+}
+
+// Block j from the end of its first-pass update: S3-S5, the second pass
+// S6-S10 against all s finished columns, S11/S12, the fallback, then R (FP32)
+// and the finished columns in FP32 and the low precision.  Main stream,
+// gated on the status word.
+int block_rest(int prec, int64_t q, int64_t w, int64_t s, const double* Yj, int64_t ldy, float* Q32, int64_t ldq,
+               float* R32, int64_t ldr, const MixedWork& ws, const Slot& sl, int blk, int32_t* info, int32_t* flags,
+               hipStream_t st) {
   const int* gate = ws.status;
   const double dq = (double)q, dw = (double)w, ds = (double)s;
-  const int64_t sp = up(s, 64);
-  MX_TRY(copy_matrix(q, w, Yj, ldy, ws.Qj, q, gate, st));
   for (int pass = 0; pass < 2; ++pass) {
-    double* X = pass == 0 ? ws.Qj : ws.T;      // block being orthogonalised
-    double* Hx = pass == 0 ? ws.H : ws.Hb;     // its projection (s x w, ld rp)
-    if (s > 0) {
-      hipLaunchKernelGGL(to_bf16_kernel, cvt_grid(ws.qp, w), dim3(256), 0, st, q, ws.qp, w, X, q, ws.B16, ws.qp,
-                         gate);
-      MX_TRY(hipGetLastError());
-      // S1/S6: H = P^T X  (BF16 x BF16 -> FP32, reduced into FP64)
-      MX_TRY(gemm_bf16_tn(ROLE_PROJ, s, w, ws.qp, 1.0f, ws.P16, ws.qp, ws.B16, ws.qp, 0.0f, Hx, ws.rp, true, ws.part,
-                          ws.part_cap, gate, st, 2.0 * dw * dq * ds));
-      hipLaunchKernelGGL(to_bf16_kernel, cvt_grid(sp, w), dim3(256), 0, st, s, sp, w, Hx, ws.rp, ws.H16, ws.rp,
-                         gate);
-      MX_TRY(hipGetLastError());
-      // S2/S7: X -= P H  (A = P^T stored k-contiguous, K = s padded with zeros)
-      MX_TRY(gemm_bf16_tn(ROLE_UPDATE, q, w, sp, -1.0f, ws.P16T, ws.rp, ws.H16, ws.rp, 1.0f, X, q, true, nullptr, 0,
-                          gate, st, 2.0 * dw * dq * ds));
+    double* X = pass == 0 ? sl.Qj : ws.T;  // block being orthogonalised
+    if (pass == 1 && s > 0) {
+      MX_RC(stage_operand(prec, q, w, ws.T, ws, sl, ws.cmax, gate, st));
+      MX_RC(project_update(prec, q, w, 0, s, ws.T, ws.Hb, ws, sl, ws.hinv, ws.cmax, ws.part, gate, st));
     }
     // S3/S8, S4/S9, S5/S10 in FP64.
     MX_TRY(gemm_tn(ROLE_GRAM, w, w, q, 1.0, X, q, X, q, 0.0, ws.W, w, (double*)ws.part, ws.part_cap / 2, gate, st,
                    (s > 0 ? 2.0 : 1.0) * dw * dw * dq));
     MX_TRY(chol_inv_wide((int)w, ws.W, w, pass == 0 ? ws.LT1 : ws.LT2, pass == 0 ? ws.XT1 : ws.XT2, ws.Rjj, ws.status,
                          pass + 1, blk, st));
-    MX_TRY(gemm_nn(ROLE_TRSM, q, w, w, 1.0, X, q, pass == 0 ? ws.XT1 : ws.XT2, w, 0.0, pass == 0 ? ws.T : ws.Qj, q,
+    MX_TRY(gemm_nn(ROLE_TRSM, q, w, w, 1.0, X, q, pass == 0 ? ws.XT1 : ws.XT2, w, 0.0, pass == 0 ? ws.T : sl.Qj, q,
                    gate, st, dw * dw * dq));
   }
   // S11 R_jj = Lb^T L^T, S12 H = H + Hb L^T, in FP64; then the fallback
   // (a breakdown redoes the block by CGS2), R (FP32) and the finished columns.
   MX_TRY(gemm_nn(ROLE_SMALL, w, w, w, 1.0, ws.LT2, w, ws.LT1, w, 0.0, ws.Rjj, w, gate, st, dw * dw * dw));
-  if (s > 0) MX_TRY(gemm_nn(ROLE_SMALL, s, w, w, 1.0, ws.Hb, ws.rp, ws.LT1, w, 1.0, ws.H, ws.rp, gate, st, dw * ds));
-  MX_TRY(block_fallback(q, w, s, Yj, ldy, Q32, ldq, ws, blk, info, flags, st));
+  if (s > 0) MX_TRY(gemm_nn(ROLE_SMALL, s, w, w, 1.0, ws.Hb, ws.rp, ws.LT1, w, 1.0, sl.H, ws.rp, gate, st, dw * ds));
+  MX_TRY(block_fallback(q, w, s, Yj, ldy, Q32, ldq, ws, sl, blk, info, flags, st));
   if (s > 0) {
-    hipLaunchKernelGGL(to_f32_kernel, dim3(grid_of(s * w)), dim3(256), 0, st, s, w, ws.H, ws.rp, R32 + s * ldr, ldr,
+    hipLaunchKernelGGL(to_f32_kernel, dim3(grid_of(s * w)), dim3(256), 0, st, s, w, sl.H, ws.rp, R32 + s * ldr, ldr,
                        gate);
     MX_TRY(hipGetLastError());
   }
   hipLaunchKernelGGL(to_f32_kernel, dim3(grid_of(w * w)), dim3(256), 0, st, w, w, ws.Rjj, w, R32 + s + s * ldr, ldr,
                      gate);
   MX_TRY(hipGetLastError());
-  hipLaunchKernelGGL(finish_block_kernel, dim3((unsigned)((q + 63) / 64), (unsigned)((w + 63) / 64)), dim3(256), 0, st,
-                     q, (int)w, ws.Qj, q, Q32, ldq, ws.P16, ws.qp, ws.P16T, ws.rp, s, gate);
+  const dim3 fgrid((unsigned)((q + 63) / 64), (unsigned)((w + 63) / 64));
+  if (prec == CQR_PREC_FP8) {
+    hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)w), dim3(kColmaxThreads), 0, st, q, sl.Qj, q,
+                       (const float*)nullptr, ws.cmax, gate);
+    MX_TRY(hipGetLastError());
+    hipLaunchKernelGGL(finish_block_fp8_kernel, fgrid, dim3(256), 0, st, q, (int)w, sl.Qj, q, Q32, ldq, ws.P8, ws.qp,
+                       ws.P8T, ws.rp, ws.blk_p, ws.blk_pt, ws.cmax, ws.pinv, s, gate);
+  } else {
+    hipLaunchKernelGGL(finish_block_kernel, fgrid, dim3(256), 0, st, q, (int)w, sl.Qj, q, Q32, ldq, ws.P16, ws.qp,
+                       ws.P16T, ws.rp, ws.blk_p, ws.blk_pt, s, gate);
+  }
   MX_TRY(hipGetLastError());
   return CQR_OK;
 }
 
-// One column block of the FP8 form: as mixed_block, with the projections and
-// updates on FP8 operands scaled per column.
-int mixed_block_fp8(int64_t q, int64_t w, int64_t s, const double* Yj, int64_t ldy, float* Q32, int64_t ldq,
-                    float* R32, int64_t ldr, const MixedWork& ws, int blk, int32_t* info, int32_t* flags,
-                    hipStream_t st) {
-  const int* gate = ws.status;
-  const double dq = (double)q, dw = (double)w, ds = (double)s;
-  const int64_t sp = up(s, 128);
-  MX_TRY(copy_matrix(q, w, Yj, ldy, ws.Qj, q, gate, st));
-  for (int pass = 0; pass < 2; ++pass) {
-    double* X = pass == 0 ? ws.Qj : ws.T;
-    double* Hx = pass == 0 ? ws.H : ws.Hb;
-    if (s > 0) {
-      hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)w), dim3(kColmaxThreads), 0, st, q, X, q, (const float*)nullptr, ws.cmax,
-                         gate);
-      MX_TRY(hipGetLastError());
-      hipLaunchKernelGGL(to_fp8_kernel, cvt_grid(ws.qp, w), dim3(256), 0, st, q, ws.qp, w, X, q,
-                         (const float*)nullptr, ws.cmax, ws.B8, ws.qp, ws.binv, gate);
-      MX_TRY(hipGetLastError());
-      // S1/S6: H = P^T X, undone scales: rows by 1/s_P, columns by 1/s_X.
-      MX_TRY(gemm_fp8_tn(ROLE_PROJ, s, w, ws.qp, 1.0f, ws.P8, ws.qp, ws.B8, ws.qp, 0.0f, Hx, ws.rp, true, ws.pinv,
-                         ws.binv, ws.part, ws.part_cap, gate, st, 2.0 * dw * dq * ds));
-      // H' = diag(1/s_P) H, then per-column scales for its FP8 copy.
-      hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)w), dim3(kColmaxThreads), 0, st, s, Hx, ws.rp, ws.pinv, ws.cmax, gate);
-      MX_TRY(hipGetLastError());
-      hipLaunchKernelGGL(to_fp8_kernel, cvt_grid(sp, w), dim3(256), 0, st, s, sp, w, Hx, ws.rp, ws.pinv,
-                         ws.cmax, ws.H8, ws.rp, ws.hinv, gate);
-      MX_TRY(hipGetLastError());
-      // S2/S7: X -= (P diag(s_P)) (diag(1/s_P) H), columns undone by 1/s_H.
-      MX_TRY(gemm_fp8_tn(ROLE_UPDATE, q, w, sp, -1.0f, ws.P8T, ws.rp, ws.H8, ws.rp, 1.0f, X, q, true, nullptr,
-                         ws.hinv, nullptr, 0, gate, st, 2.0 * dw * dq * ds));
-    }
-    MX_TRY(gemm_tn(ROLE_GRAM, w, w, q, 1.0, X, q, X, q, 0.0, ws.W, w, (double*)ws.part, ws.part_cap / 2, gate, st,
-                   (s > 0 ? 2.0 : 1.0) * dw * dw * dq));
-    MX_TRY(chol_inv_wide((int)w, ws.W, w, pass == 0 ? ws.LT1 : ws.LT2, pass == 0 ? ws.XT1 : ws.XT2, ws.Rjj, ws.status,
-                         pass + 1, blk, st));
-    MX_TRY(gemm_nn(ROLE_TRSM, q, w, w, 1.0, X, q, pass == 0 ? ws.XT1 : ws.XT2, w, 0.0, pass == 0 ? ws.T : ws.Qj, q,
-                   gate, st, dw * dw * dq));
-  }
-  MX_TRY(gemm_nn(ROLE_SMALL, w, w, w, 1.0, ws.LT2, w, ws.LT1, w, 0.0, ws.Rjj, w, gate, st, dw * dw * dw));
-  if (s > 0) MX_TRY(gemm_nn(ROLE_SMALL, s, w, w, 1.0, ws.Hb, ws.rp, ws.LT1, w, 1.0, ws.H, ws.rp, gate, st, dw * ds));
-  MX_TRY(block_fallback(q, w, s, Yj, ldy, Q32, ldq, ws, blk, info, flags, st));
+// Block j: its copy of Y, the first pass against all s finished columns,
+// then the rest.
+int block_plain(int prec, int64_t q, int64_t w, int64_t s, const double* Yj, int64_t ldy, float* Q32, int64_t ldq,
+                float* R32, int64_t ldr, const MixedWork& ws, int blk, int32_t* info, int32_t* flags,
+                hipStream_t st) {
+  const Slot& sl = ws.slot;
+  MX_TRY(copy_matrix(q, w, Yj, ldy, sl.Qj, q, ws.status, st));
   if (s > 0) {
-    hipLaunchKernelGGL(to_f32_kernel, dim3(grid_of(s * w)), dim3(256), 0, st, s, w, ws.H, ws.rp, R32 + s * ldr, ldr,
-                       gate);
-    MX_TRY(hipGetLastError());
+    MX_RC(stage_operand(prec, q, w, sl.Qj, ws, sl, ws.cmax, ws.status, st));
+    MX_RC(project_update(prec, q, w, 0, s, sl.Qj, sl.H, ws, sl, ws.hinv, ws.cmax, ws.part, ws.status, st));
   }
-  hipLaunchKernelGGL(to_f32_kernel, dim3(grid_of(w * w)), dim3(256), 0, st, w, w, ws.Rjj, w, R32 + s + s * ldr, ldr,
-                     gate);
-  MX_TRY(hipGetLastError());
-  hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)w), dim3(kColmaxThreads), 0, st, q, ws.Qj, q, (const float*)nullptr, ws.cmax,
-                     gate);
-  MX_TRY(hipGetLastError());
-  hipLaunchKernelGGL(finish_block_fp8_kernel, dim3((unsigned)((q + 63) / 64), (unsigned)((w + 63) / 64)), dim3(256),
-                     0, st, q, (int)w, ws.Qj, q, Q32, ldq, ws.P8, ws.qp, ws.P8T, ws.rp, ws.cmax, ws.pinv, s, gate);
-  MX_TRY(hipGetLastError());
-  return CQR_OK;
+  return block_rest(prec, q, w, s, Yj, ldy, Q32, ldq, R32, ldr, ws, sl, blk, info, flags, st);
 }
 
 }  // namespace
@@ -586,11 +636,16 @@ int cqr_factor_mixed(int64_t q, int64_t r, int64_t b, int prec, const double* Y,
   for (int64_t blk = 0; blk < k; ++blk) {
     const int64_t s = blk * b;
     const int64_t w = (r - s < b) ? r - s : b;
-    const int rc = (prec == CQR_PREC_FP8)
-                       ? mixed_block_fp8(q, w, s, Y + s * ldy, ldy, Q, ldq, R, ldr, ws, (int)blk, info, block_flags, st)
-                       : mixed_block(q, w, s, Y + s * ldy, ldy, Q, ldq, R, ldr, ws, (int)blk, info, block_flags, st);
+    const int rc = block_plain(prec, q, w, s, Y + s * ldy, ldy, Q, ldq, R, ldr, ws, (int)blk, info, block_flags, st);
     if (rc) return rc;
   }
+  return CQR_OK;
+}
+
+// Testing aid: storage order of the finished low-precision columns.
+int cqr_set_mixed_layout(int tiled) {
+  if (tiled != 0 && tiled != 1) return -1;
+  g_tiled = tiled != 0;
   return CQR_OK;
 }
 

@@ -256,3 +256,26 @@ def test_c3_n65536_properties(prec):
     r = (Y @ x - rhs).abs().max()
     hpl = float(r / ((rs + Y.diagonal().abs()).max() * x.abs().max() * n * EPS))
     assert hpl < 16, hpl
+
+
+@pytest.mark.parametrize("prec,n,b", [(cqr.PREC_BF16, 2048, 256), (cqr.PREC_BF16, 1000, 256),
+                                      (cqr.PREC_FP8, 2048, 256), (cqr.PREC_FP8, 776, 128)])
+def test_tiled_column_storage_is_bit_identical(prec, n, b):
+    """The tiled storage of the finished low-precision columns changes only
+    where the products read their operand from, not the order of any sum:
+    Q, R and info are the same bits as with column-major storage (ragged
+    sizes and block widths that are not multiples of the 128-column blocks
+    included; block widths whose products all take the wide GEMM tile, as the
+    tiled storage does)."""
+    Yd = to_dev(inputs.diag_dominant(n, seed=71 + n))
+    out = []
+    try:
+        for tiled in (False, True):
+            cqr.set_mixed_layout(tiled)
+            Q, R, info = cqr.qr_mixed(Yd, b, prec=prec)
+            torch.cuda.synchronize()
+            assert info == 0
+            out.append((Q.clone(), R.clone()))
+    finally:
+        cqr.set_mixed_layout(True)
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
