@@ -319,17 +319,20 @@ gemm_lp_wide_kernel(int64_t M, int64_t N, int64_t K, float alpha, const E* __res
     if constexpr (F8) {
       // One v_mfma_scale_f32_16x16x128_f8f6f4 (E4M3 operands, unit scales)
       // per tile and stage, a quarter of the instructions of the 16x16x32
-      // form at twice its rate.  Lane group lg supplies, for each 32-k
-      // quarter q, bytes 32 q + 8 lg .. + 7 of its row of A and column of B
-      // (half of chunk 2 q + lg / 2): A and B share that k order, which is
-      // all the product needs.
+      // form at twice its rate.  Lane group lg supplies bytes 32 lg .. + 31
+      // of its row of A and column of B (chunks 2 lg and 2 lg + 1, two 128-bit
+      // reads that, like the BF16 operand reads, put the 16 lanes of a group
+      // on 16 distinct 16-byte bank groups): A and B share that k order,
+      // which is all the product needs.
+      typedef int i4v __attribute__((ext_vector_type(4)));
       auto frag = [&](const char* base, int x) {
+        const i4v lo = *(const i4v*)(base + chunk_off(2 * lg, x));
+        const i4v hi = *(const i4v*)(base + chunk_off(2 * lg + 1, x));
         v8i f;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const long w = *(const long*)(base + chunk_off(2 * q + (lg >> 1), x) + 8 * (lg & 1));
-          f[2 * q] = (int)w;
-          f[2 * q + 1] = (int)(w >> 32);
+        for (int e = 0; e < 4; ++e) {
+          f[e] = lo[e];
+          f[4 + e] = hi[e];
         }
         return f;
       };
