@@ -252,7 +252,10 @@ class QRSolve(torch.autograd.Function):
     """x = A^{-1} b for a batch of square systems A (..., n, n), b (..., n),
     n <= 512, through the batched CGS-QR factorisation and solve; the backward
     pass is the library's adjoint kernel (lambda = A^{-T} g from the stored
-    factors, dA = -lambda x^T, db = lambda)."""
+    factors, dA = -lambda x^T, db = lambda).  ``n`` above the batched plan's
+    largest size raises ValueError.  A block that breaks down is redone by the
+    column-by-column fallback inside the kernel; the per-matrix ``info`` of
+    the batch (nonzero on a fallback) stays on the device and is not read."""
 
     @staticmethod
     def forward(ctx, A, b):
@@ -262,6 +265,11 @@ class QRSolve(torch.autograd.Function):
         nb, n, n2 = A3.shape
         if n != n2 or b2.shape != (nb, n):
             raise ValueError("A must be (..., n, n) and b (..., n)")
+        # The kernels skip a matrix above the plan's largest size (info = -1,
+        # x left as b); refuse it here instead of returning that silently.
+        top = get_plan(A.dtype)["hi"][-1]
+        if n > top:
+            raise ValueError("n = %d is above the batched plan's largest size %d" % (n, top))
         batch = PackedBatch([n] * nb, dtype=A.dtype, device=A.device)
         # Column-major storage of A_i is row-major storage of A_i^T.
         batch.A.view(nb, n, n).copy_(A3.detach().transpose(1, 2))

@@ -319,15 +319,17 @@ gemm_lp_wide_kernel(int64_t M, int64_t N, int64_t K, float alpha, const E* __res
     if constexpr (F8) {
       // One v_mfma_scale_f32_16x16x128_f8f6f4 (E4M3 operands, unit scales)
       // per tile and stage, a quarter of the instructions of the 16x16x32
-      // form at twice its rate.  Lane group lg supplies bytes 32 lg .. + 31
-      // of its row of A and column of B (chunks 2 lg and 2 lg + 1, two 128-bit
-      // reads that, like the BF16 operand reads, put the 16 lanes of a group
-      // on 16 distinct 16-byte bank groups): A and B share that k order,
+      // form at twice its rate.  The instruction takes 32 k-bytes of its row
+      // of A and column of B from each lane group lg; here they are the
+      // 16-byte chunks lg and lg + 4 of the stage, read as two 128-bit reads
+      // whose addresses follow the BF16 operand reads exactly (lane group lg
+      // on chunk c0 + lg of an aligned run of four), the pattern that keeps
+      // those reads free of bank conflicts.  A and B share this k order,
       // which is all the product needs.
       typedef int i4v __attribute__((ext_vector_type(4)));
       auto frag = [&](const char* base, int x) {
-        const i4v lo = *(const i4v*)(base + chunk_off(2 * lg, x));
-        const i4v hi = *(const i4v*)(base + chunk_off(2 * lg + 1, x));
+        const i4v lo = *(const i4v*)(base + chunk_off(lg, x));
+        const i4v hi = *(const i4v*)(base + chunk_off(lg + 4, x));
         v8i f;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {

@@ -161,7 +161,7 @@ trsv_lookback_kernel(int64_t n, const TR* __restrict__ R, int64_t ldr, const dou
       for (int c = 0; c < 16; ++c) cur[c] = rt[c];
       if (J - 1 > I) load_tile(J - 1);
 #pragma unroll
-      for (int c = 0; c < 16; ++c) acc += (double)cur[c] * wave_bcast(xv, c);
+      for (int c = 0; c < 16; ++c) acc += (double)cur[c] * row_bcast(xv, c);  // xv repeats every 16 lanes
     }
     next = lo - 1;
   }

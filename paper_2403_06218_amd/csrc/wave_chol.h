@@ -1,7 +1,7 @@
 // Cholesky factorisation of a small SPD block (WP <= 32) held by one wave:
 // lane i < WP owns row i.  Shared by the single-matrix factor kernel (its
 // 16 x 16 diagonal blocks) and the batched form (its block Grams); and the
-// wave broadcast used by the solve kernels.
+// wave broadcasts used by the solve kernels.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,6 +18,56 @@ __device__ __forceinline__ float wave_bcast(float x, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
 }
 
+// Lane 16 r + N's value to every lane of its row of 16 (lanes 16 r .. 16 r +
+// 15): the DPP row_newbcast control, one VALU move straight into a vector
+// register (v_mov_b64_dpp for a double).  A readlane goes through a scalar
+// register instead, with a wait before every use and one scalar pair reused
+// by every broadcast, so that a run of them executes strictly one after the
+// other.
+template <int N>
+__device__ __forceinline__ double dpp_row_bcast(double x) {
+  static_assert(N >= 0 && N < 16, "row lane");
+  const long v = __builtin_amdgcn_mov_dpp(__builtin_bit_cast(long, x), 0x150 + N, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, v);
+}
+template <int N>
+__device__ __forceinline__ float dpp_row_bcast(float x) {
+  static_assert(N >= 0 && N < 16, "row lane");
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x150 + N, 0xF, 0xF, false));
+}
+
+// row_bcast(x, j): dpp_row_bcast<j>(x) for a j that is a constant once the
+// caller's loops are unrolled (the switch then folds away).
+template <typename T>
+__device__ __forceinline__ T row_bcast(T x, int j) {
+  switch (j) {
+    case 0: return dpp_row_bcast<0>(x);
+    case 1: return dpp_row_bcast<1>(x);
+    case 2: return dpp_row_bcast<2>(x);
+    case 3: return dpp_row_bcast<3>(x);
+    case 4: return dpp_row_bcast<4>(x);
+    case 5: return dpp_row_bcast<5>(x);
+    case 6: return dpp_row_bcast<6>(x);
+    case 7: return dpp_row_bcast<7>(x);
+    case 8: return dpp_row_bcast<8>(x);
+    case 9: return dpp_row_bcast<9>(x);
+    case 10: return dpp_row_bcast<10>(x);
+    case 11: return dpp_row_bcast<11>(x);
+    case 12: return dpp_row_bcast<12>(x);
+    case 13: return dpp_row_bcast<13>(x);
+    case 14: return dpp_row_bcast<14>(x);
+    default: return dpp_row_bcast<15>(x);
+  }
+}
+
+// Lane j's value for lanes 0 .. WP-1: the row broadcast when WP <= 16 (all
+// consumers sit in the first row of 16 lanes), else readlane.
+template <int WP, typename T>
+__device__ __forceinline__ T small_bcast(T x, int j) {
+  if constexpr (WP <= 16) return row_bcast(x, j);
+  else return wave_bcast(x, j);
+}
+
 // W = L L^T computed as W = U D U^T (U unit lower, D diagonal), then
 // L = U D^{1/2}.  On entry lane i holds a[j] = W(i, j) for j <= i (lanes >= WP
 // and entries j > i may hold anything).  On return
@@ -26,9 +76,11 @@ __device__ __forceinline__ float wave_bcast(float x, int l) {
 // > 0 (NaN included); the outputs are then meaningless.
 //
 // Step k needs one division (1 / d_k) on its critical chain; the broadcasts of
-// column k (readlane) depend only on values present at the start of the step,
-// so they overlap the division, and the square roots are all taken at the
-// end, one per lane.
+// column k depend only on values present at the start of the step, so they
+// overlap the division, and the square roots are all taken at the end, one
+// per lane.  The return value, lii and linv are those of lanes < WP; with
+// WP <= 16 the other lanes take their broadcasts from their own row of 16
+// lanes, so what they compute is meaningless.
 template <typename T, int WP>
 __device__ __forceinline__ bool wave_chol(T (&a)[WP], T& lii, T& linv, int lane) {
   // Every update runs unpredicated on all lanes: it also rewrites entries
@@ -39,13 +91,13 @@ __device__ __forceinline__ bool wave_chol(T (&a)[WP], T& lii, T& linv, int lane)
   T dmine = T(1);
 #pragma unroll
   for (int k = 0; k < WP; ++k) {
-    const T d = wave_bcast(a[k], k);
+    const T d = small_bcast<WP>(a[k], k);
     ok = ok && (d > T(0));
     const T r = T(1) / d;
     const T c = a[k];   // lane i > k: W^(k)(i, k) = u_ik d_k
     const T u = c * r;  // u_ik
 #pragma unroll
-    for (int j = k + 1; j < WP; ++j) a[j] -= u * wave_bcast(c, j);
+    for (int j = k + 1; j < WP; ++j) a[j] -= u * small_bcast<WP>(c, j);
     dmine = (lane == k) ? d : dmine;
     a[k] = u;
   }
@@ -53,7 +105,7 @@ __device__ __forceinline__ bool wave_chol(T (&a)[WP], T& lii, T& linv, int lane)
   lii = s;
   linv = T(1) / s;
 #pragma unroll
-  for (int j = 0; j < WP; ++j) a[j] *= wave_bcast(s, j);
+  for (int j = 0; j < WP; ++j) a[j] *= small_bcast<WP>(s, j);
   return ok;
 }
 

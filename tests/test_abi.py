@@ -105,3 +105,14 @@ def test_batched_validation_and_plan():
     assert batched.get_plan(torch.float64) == {"hi": [100, 256], "inst": [f64_256, f64_256]}
     assert batched.block_width(100) == insts[f64_256]["bw"]
     batched.set_plan(torch.float64, old["hi"], old["inst"])
+
+
+def test_qr_solve_rejects_sizes_above_the_plan():
+    # A host-side check before any device work: above the plan's largest size
+    # the kernels would skip the matrix and leave x = b.
+    from paper_2403_06218_amd import batched
+    top = batched.get_plan(torch.float64)["hi"][-1]
+    A = torch.zeros(2, top + 1, top + 1, dtype=torch.float64)
+    b = torch.zeros(2, top + 1, dtype=torch.float64)
+    with pytest.raises(ValueError, match="largest size"):
+        batched.qr_solve(A, b)
