@@ -156,12 +156,12 @@ chol_inv_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __rest
       for (int k = 0; k < 15; ++k) {
         const double mik = (lane > k) ? a[k] * linv : 0.0;
 #pragma unroll
-        for (int j = 0; j <= k; ++j) xr[j] -= mik * wave_bcast(xr[j], k);
+        for (int j = 0; j <= k; ++j) xr[j] -= mik * row_bcast(xr[j], k);
       }
       // X(i, j) = (M^{-1})_ij / L_jj, stored transposed above the diagonal.
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        const double djinv = wave_bcast(linv, j);
+        const double djinv = row_bcast(linv, j);
         if (lane < 16 && j < lane) sA[(c0 + j) * kCLD + c0 + lane] = xr[j] * djinv;
       }
     } else {
@@ -272,12 +272,12 @@ chol_inv16_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __re
   for (int k = 0; k < 15; ++k) {
     const double mik = (lane > k) ? a[k] * linv : 0.0;
 #pragma unroll
-    for (int j = 0; j <= k; ++j) xr[j] -= mik * wave_bcast(xr[j], k);
+    for (int j = 0; j <= k; ++j) xr[j] -= mik * row_bcast(xr[j], k);
   }
   // LT(j, i) = L(i, j) and XT(j, i) = X(i, j) = (M^{-1})_ij / L_jj.
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
-    const double djinv = wave_bcast(linv, j);
+    const double djinv = row_bcast(linv, j);
     if (lane < b && j < b) {
       LT[j + (int64_t)lane * ldo] = (j < lane) ? a[j] : ((j == lane) ? lii : 0.0);
       XT[j + (int64_t)lane * ldo] = (j < lane) ? xr[j] * djinv : ((j == lane) ? linv : 0.0);
