@@ -58,7 +58,8 @@ def parse():
     p.add_argument("--no-fp64", action="store_true", help="profiling aid: skip the FP64 n x n measurement")
     p.add_argument("--counters-only", action="store_true",
                    help="profiler driver: one untimed FP64 step (--b) and, unless --no-mixed, one BF16 and one FP8 "
-                        "factorisation of the diagonally dominant matrix; no checks, no JSON line")
+                        "factorisation of the diagonally dominant matrix, and unless --no-batched one FP64 and one "
+                        "FP32 call of the batched form; no checks, no JSON line")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="before the run, copy this many MiB device-to-device once (reference kernel for HBM counters)")
     return p.parse_args()
@@ -678,6 +679,22 @@ def counters_only(args, torch, cqr):
             _, _, info, _ = cqr.qr_mixed_async(Y, args.mixed_b, prec=prec)
             torch.cuda.synchronize()
             print("counters-only: prec=%d n=%d b=%d info=%d" % (prec, n, args.mixed_b, int(info[0])), flush=True)
+    if not args.no_batched:
+        # The batched form's workload, one eager call per element type with
+        # the library's default plan.
+        del Y, rhs
+        torch.cuda.empty_cache()
+        from paper_2403_06218_amd import batched, inputs
+        sizes = inputs.batch_sizes(10000, 8, 256, seed=args.seed)
+        for dt in (torch.float64, torch.float32):
+            batch = batched.PackedBatch(sizes, dtype=dt)
+            batched._fill(batch, args.seed + 100)
+            work = torch.empty(max(batched.workspace_size(batch.count), 1), dtype=torch.uint8, device=dev)
+            batched.factor_solve(batch, work)
+            torch.cuda.synchronize()
+            print("counters-only: batched %s, %d matrices, %d fallbacks" % (
+                dt, batch.count, int((batch.info > 0).sum())), flush=True)
+            del batch, work
 
 
 def main():
