@@ -80,14 +80,15 @@ hipError_t gemm_fp8_tn(Role role, int64_t M, int64_t N, int64_t K, float alpha, 
 // Lower Cholesky W = L L^T of a b x b SPD matrix (b <= 128) and the inverse of
 // L, in one workgroup.  Writes LT = L^T and XT = (L^{-1})^T (both b x b,
 // leading dimension b, upper triangular with zero strictly-lower part).  On a
-// pivot that is not > 0 sets status[0] = code, status[1] = blk.
+// pivot that is not > 0 sets status[0] = code, status[1] = blk.  With f32 the
+// factorisation runs in FP32 arithmetic (FP64 input and outputs; b > 16).
 hipError_t chol_inv(int b, const double* W, int64_t ldw, double* LT, double* XT, int* status, int code, int blk,
-                    hipStream_t s);
+                    hipStream_t s, bool f32 = false);
 // The same for b <= 256 through a 2 x 2 block split at 128 (MFMA GEMMs for the
-// off-diagonal blocks and the Schur complement).  W's trailing block is
-// overwritten; tmp holds 128 x (b - 128) doubles.
+// off-diagonal blocks and the Schur complement, in FP64).  W's trailing block
+// is overwritten; tmp holds 128 x (b - 128) doubles.
 hipError_t chol_inv_wide(int b, double* W, int64_t ldw, double* LT, double* XT, double* tmp, int* status, int code,
-                         int blk, hipStream_t s);
+                         int blk, hipStream_t s, bool f32 = false);
 
 // Row-streaming steps of CGS-CQR2 for a narrow block (w <= 16 columns, s <= 128
 // basis columns, q >= 16384 rows): tall_eligible tells whether they apply.

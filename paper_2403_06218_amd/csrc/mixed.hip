@@ -532,11 +532,13 @@ int block_rest(int prec, int64_t q, int64_t w, int64_t s, const double* Yj, int6
       MX_RC(stage_operand(prec, q, w, ws.T, ws, sl, ws.cmax, gate, st));
       MX_RC(project_update(prec, q, w, 0, s, ws.T, ws.Hb, ws, sl, ws.hinv, ws.cmax, ws.part, gate, st));
     }
-    // S3/S8, S4/S9, S5/S10 in FP64.
+    // S3/S8 (Gram) and S5/S10 (TRSM) in FP64 on the FP64 block; S4/S9 the
+    // Cholesky factorisation in FP32 arithmetic, whose rounding is far below
+    // the projections' BF16/FP8 rounding that the factors carry anyway.
     MX_TRY(gemm_tn(ROLE_GRAM, w, w, q, 1.0, X, q, X, q, 0.0, ws.W, w, (double*)ws.part, ws.part_cap / 2, gate, st,
                    (s > 0 ? 2.0 : 1.0) * dw * dw * dq));
     MX_TRY(chol_inv_wide((int)w, ws.W, w, pass == 0 ? ws.LT1 : ws.LT2, pass == 0 ? ws.XT1 : ws.XT2, ws.Rjj, ws.status,
-                         pass + 1, blk, st));
+                         pass + 1, blk, st, /*f32=*/true));
     MX_TRY(gemm_nn(ROLE_TRSM, q, w, w, 1.0, X, q, pass == 0 ? ws.XT1 : ws.XT2, w, 0.0, pass == 0 ? ws.T : sl.Qj, q,
                    gate, st, dw * dw * dq));
   }
