@@ -352,7 +352,7 @@ hipError_t chol_inv(int b, const double* W, int64_t ldw, double* LT, double* XT,
 // Writes LT = [L11^T U12; 0 L22^T] and XT = [X11^T X21^T; 0 X22^T] (ld b).
 // W's trailing block is overwritten by S; tmp holds b1 x b2 doubles.
 hipError_t chol_inv_wide(int b, double* W, int64_t ldw, double* LT, double* XT, double* tmp, int* status, int code,
-                         int blk, hipStream_t s, bool f32) {
+                         int blk, hipStream_t s, bool f32, bool lower_zero) {
   if (b <= kCB) return chol_inv(b, W, ldw, LT, XT, status, code, blk, s, f32);
   if (b > 2 * kCB) return hipErrorInvalidValue;
   const int b1 = kCB, b2 = b - kCB;
@@ -380,7 +380,9 @@ hipError_t chol_inv_wide(int b, double* W, int64_t ldw, double* LT, double* XT, 
   if ((e = gemm_nn(ROLE_CHOL, b1, b2, b2, -1.0, tmp, b1, XT + b1 + (int64_t)b1 * b, b, 0.0, X12, b, status, s,
                    2.0 * d1 * d2 * d2)) != hipSuccess)
     return e;
-  // Strictly lower blocks of LT and XT.
+  // Strictly lower blocks of LT and XT (nothing else writes them, so a
+  // caller whose buffers start zero need not clear them again).
+  if (lower_zero) return hipSuccess;
   if ((e = zero_matrix(b2, b1, LT + b1, b, s)) != hipSuccess) return e;
   return zero_matrix(b2, b1, XT + b1, b, s);
 }

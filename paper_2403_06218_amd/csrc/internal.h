@@ -86,9 +86,11 @@ hipError_t chol_inv(int b, const double* W, int64_t ldw, double* LT, double* XT,
                     hipStream_t s, bool f32 = false);
 // The same for b <= 256 through a 2 x 2 block split at 128 (MFMA GEMMs for the
 // off-diagonal blocks and the Schur complement, in FP64).  W's trailing block
-// is overwritten; tmp holds 128 x (b - 128) doubles.
+// is overwritten; tmp holds 128 x (b - 128) doubles.  lower_zero: the strictly
+// lower (b-128) x 128 blocks of LT and XT already hold zeros (they are never
+// written), so they are not cleared.
 hipError_t chol_inv_wide(int b, double* W, int64_t ldw, double* LT, double* XT, double* tmp, int* status, int code,
-                         int blk, hipStream_t s, bool f32 = false);
+                         int blk, hipStream_t s, bool f32 = false, bool lower_zero = false);
 
 // Row-streaming steps of CGS-CQR2 for a narrow block (w <= 16 columns, s <= 128
 // basis columns, q >= 16384 rows): tall_eligible tells whether they apply.

@@ -73,6 +73,7 @@ struct MixedWork {
   size_t part_cap;
   void* fb;         // breakdown fallback workspace (counters first; zero at the start of a call)
   int64_t qp, rp;
+  int64_t b;        // the block width of the call (every block but a ragged last one)
   // Tiled storage of the finished columns (see gemm_bf16_tn): a_blk of P
   // (K = qp rows, 128-column blocks) and of P^T (K = rp, 128-row blocks);
   // 0 = column-major.
@@ -93,6 +94,7 @@ size_t mixed_layout(int64_t q, int64_t r, int64_t b, int prec, char* base, Mixed
   // layout's column blocks; a multiple of the BF16 and FP8 k-stages).
   o->qp = up(q > 0 ? q : 1, 128);
   o->rp = up(r > 0 ? r : 1, 128);
+  o->b = b;
   const bool tiled = g_tiled;
   o->blk_p = tiled ? o->qp * 128 : 0;
   o->blk_pt = tiled ? o->rp * 128 : 0;
@@ -534,11 +536,15 @@ int block_rest(int prec, int64_t q, int64_t w, int64_t s, const double* Yj, int6
     }
     // S3/S8 (Gram) and S5/S10 (TRSM) in FP64 on the FP64 block; S4/S9 the
     // Cholesky factorisation in FP32 arithmetic, whose rounding is far below
-    // the projections' BF16/FP8 rounding that the factors carry anyway.
+    // the projections' BF16/FP8 rounding that the factors carry anyway.  The
+    // strictly lower blocks of the factors' buffers are never written, so
+    // they keep the zeros of the cleared workspace for every block of the
+    // call's width (a ragged last block lays the buffers out with another
+    // leading dimension and clears them).
     MX_TRY(gemm_tn(ROLE_GRAM, w, w, q, 1.0, X, q, X, q, 0.0, ws.W, w, (double*)ws.part, ws.part_cap / 2, gate, st,
                    (s > 0 ? 2.0 : 1.0) * dw * dw * dq));
     MX_TRY(chol_inv_wide((int)w, ws.W, w, pass == 0 ? ws.LT1 : ws.LT2, pass == 0 ? ws.XT1 : ws.XT2, ws.Rjj, ws.status,
-                         pass + 1, blk, st, /*f32=*/true));
+                         pass + 1, blk, st, /*f32=*/true, /*lower_zero=*/w == ws.b));
     MX_TRY(gemm_nn(ROLE_TRSM, q, w, w, 1.0, X, q, pass == 0 ? ws.XT1 : ws.XT2, w, 0.0, pass == 0 ? ws.T : sl.Qj, q,
                    gate, st, dw * dw * dq));
   }
