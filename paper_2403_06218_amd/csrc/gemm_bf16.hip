@@ -55,6 +55,22 @@ __device__ __forceinline__ void wait_vmcnt() {
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
+// Barrier between two stages of a ring.  __syncthreads() carries a
+// workgroup-scope release fence, which waits for every outstanding memory
+// operation of the wave (vmcnt(0)), the LDS-DMA loads of later stages
+// included, and so drains the prefetch ring at every stage.  Here each wave
+// has already waited for its own loads of the stage about to be read
+// (wait_vmcnt), its LDS reads of the stage just computed are complete
+// (lgkmcnt(0), so no load issued after the barrier overwrites a slot that is
+// still being read), and compiler-only fences keep LDS accesses on their side
+// of the hardware barrier.
+__device__ __forceinline__ void stage_barrier() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt not waited for
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // Tile height of the wide kernel: 256 for projections with at least 12288
 // rows of output (measured: 5-15% faster there, slower for fewer rows).
 int wide_mt(int role, int64_t M) { return (role == ROLE_PROJ && M >= 12288) ? 256 : 128; }
@@ -163,7 +179,7 @@ gemm_bf16_kernel(int64_t M, int64_t N, int64_t K, float alpha, const __bf16* __r
   auto step = [&](int st, auto cur, auto nxt) {
     if (st + S - 2 < nst) wait_vmcnt<(S - 2) * PER_STAGE>();
     else wait_vmcnt<0>();
-    __syncthreads();
+    stage_barrier();
     if (st + S - 1 < nst) issue(st + S - 1, nxt);
     compute(cur);
   };
@@ -211,20 +227,22 @@ gemm_bf16_kernel(int64_t M, int64_t N, int64_t K, float alpha, const __bf16* __r
 }
 
 // 128 x 256 tile with 2 x 4 waves (64 x 64 per wave; MT_ = 256: 256 x 256
-// with 128 x 64 per wave and rings of 3 + 2 stages, for the projections of
-// the later blocks, whose s x b output needs few splits) and the loads split by
-// wave: waves 0-3 copy A (the row panel, unique to the workgroup and streamed
-// from HBM, loaded non-temporal) into a 6-slot ring, waves 4-7 copy B (shared
-// by all workgroups, served by L2) into a 2-slot ring.  Each wave's vmcnt then counts only its
-// own operand, so A keeps 5 stages (80 KiB) in flight while B is waited for
-// one stage ahead; the two rings fill the 160 KiB of LDS.
+// with 128 x 64 per wave, for the projections of the later blocks, whose
+// s x b output needs few splits) and the loads split by wave: waves 0-3 copy A
+// (the row panel, unique to the workgroup and streamed from HBM, loaded
+// non-temporal), waves 4-7 copy B (shared by all workgroups, served by L2),
+// each into a ring of SA / SB slots, so each wave's vmcnt counts only its own
+// operand.  Each operand is loaded one stage ahead (two slots each): rings
+// that let A run further ahead (3-6 slots, with a barrier that does not drain
+// the loads) were measured slower, its prefetches delaying the loads of B
+// that the next stage waits for, and a deeper B ring did not help.
 //
 // E is __bf16 (v_mfma_f32_16x16x32_bf16, 64 k per stage) or fp8 (OCP E4M3
 // bytes, v_mfma_scale_f32_16x16x128_f8f6f4, 128 k per stage); both give 128 bytes
 // per column per stage, so the LDS layout is the same.  rs / cs (may be
 // NULL) multiply accumulator row m / column n before alpha: the inverse
 // power-of-two scales of the FP8 operands.
-template <typename E, int ROLE, int OUT, int SA = 6, int SB = 2, int MT_ = 128>
+template <typename E, int ROLE, int OUT, int SA = 2, int SB = 2, int MT_ = 128>
 __global__ void __launch_bounds__(512, 1)
 gemm_lp_wide_kernel(int64_t M, int64_t N, int64_t K, float alpha, const E* __restrict__ A, int64_t lda, int64_t a_blk,
                     const E* __restrict__ B, int64_t ldb, float beta, void* C, int64_t ldc, int64_t kchunk,
@@ -378,7 +396,7 @@ gemm_lp_wide_kernel(int64_t M, int64_t N, int64_t K, float alpha, const E* __res
       if (st + SB - 2 < nst) wait_vmcnt<(SB - 2) * BINS>();
       else wait_vmcnt<0>();
     }
-    __syncthreads();
+    stage_barrier();
     if (aloader) {
       if (st + SA - 1 < nst) issueA(st + SA - 1, na);
     } else {
@@ -501,7 +519,7 @@ hipError_t launch_bf16_tile(int64_t M, int64_t N, int64_t K, float alpha, const 
     if constexpr (ROLE == ROLE_PROJ) {
       if (wide_mt(ROLE, M) == 256) {
         const dim3 grid((unsigned)((M + 255) / 256), (unsigned)((N + 255) / 256), (unsigned)nsplit);
-        hipLaunchKernelGGL((gemm_lp_wide_kernel<__bf16, ROLE, OUT, 3, 2, 256>), grid, dim3(512), 0, s, M, N, K, alpha,
+        hipLaunchKernelGGL((gemm_lp_wide_kernel<__bf16, ROLE, OUT, 2, 2, 256>), grid, dim3(512), 0, s, M, N, K, alpha,
                            A, lda, a_blk, B, ldb, beta, C, ldc, kchunk, part, (const float*)nullptr, (const float*)nullptr,
                            gate);
         return hipGetLastError();
@@ -650,10 +668,10 @@ hipError_t gemm_fp8_tn(Role role, int64_t M, int64_t N, int64_t K, float alpha, 
   const int slot = prof_begin(s);
   if (mt == 256) {
     if (nsplit > 1)
-      hipLaunchKernelGGL((gemm_lp_wide_kernel<fp8_t, ROLE_PROJ, 0, 3, 2, 256>), grid, dim3(512), 0, s, M, N, K, alpha,
+      hipLaunchKernelGGL((gemm_lp_wide_kernel<fp8_t, ROLE_PROJ, 0, 2, 2, 256>), grid, dim3(512), 0, s, M, N, K, alpha,
                          a8, lda, a_blk, b8, ldb, beta, C, ldc, kchunk, part, rs, cs, gate);
     else if (c_is_f64)
-      hipLaunchKernelGGL((gemm_lp_wide_kernel<fp8_t, ROLE_PROJ, 2, 3, 2, 256>), grid, dim3(512), 0, s, M, N, K, alpha,
+      hipLaunchKernelGGL((gemm_lp_wide_kernel<fp8_t, ROLE_PROJ, 2, 2, 2, 256>), grid, dim3(512), 0, s, M, N, K, alpha,
                          a8, lda, a_blk, b8, ldb, beta, C, ldc, kchunk, part, rs, cs, gate);
     else
       return hipErrorInvalidValue;
