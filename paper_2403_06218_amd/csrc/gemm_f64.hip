@@ -42,6 +42,7 @@ namespace cqr {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
 
@@ -238,7 +239,12 @@ __device__ __forceinline__ int mc_index(int m, int k) {
 
 // Same contract as gemm_reg_kernel; requires K and kchunk multiples of 16,
 // 16-byte aligned A and B, even lda and ldb, and (for !TA) even M.
-template <int ROLE, bool TA, int MT, int NT, int S, int OCC, int WM = 2, int WN = 2>
+// F32C: the operands are rounded to FP32 as they leave LDS and multiplied by
+// v_mfma_f32_16x16x4_f32 (twice the FP64 matrix rate) with FP32 accumulation
+// over the workgroup's reduction range; the partial sums and the epilogue stay
+// FP64.  The operand layout is the FP64 one; the FP32 accumulator holds rows
+// 4(l/16) + v of the permuted operand rows, i.e. tile rows l/16 + 4v.
+template <int ROLE, bool TA, int MT, int NT, int S, int OCC, int WM = 2, int WN = 2, bool F32C = false>
 __global__ void __launch_bounds__(64 * WM * WN, OCC)
 gemm_dma_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A, int64_t lda,
                 const double* __restrict__ B, int64_t ldb, double beta, double* C, int64_t ldc, int64_t kchunk,
@@ -325,11 +331,12 @@ gemm_dma_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __r
     for (int t = 0; t < BINS; ++t) dma16(gb + boff[t], lb + (wave * BINS + t) * 128);
   };
 
-  d4 acc[SM][SN];
+  using Acc = std::conditional_t<F32C, f4, d4>;
+  Acc acc[SM][SN];
 #pragma unroll
   for (int i = 0; i < SM; ++i)
 #pragma unroll
-    for (int j = 0; j < SN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < SN; ++j) acc[i][j] = Acc{0, 0, 0, 0};
 
   auto compute = [&](auto slot) {
     const double* cA = slotA(slot);
@@ -348,8 +355,12 @@ gemm_dma_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __r
 #pragma unroll
       for (int i = 0; i < SM; ++i)
 #pragma unroll
-        for (int j = 0; j < SN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < SN; ++j) {
+          if constexpr (F32C)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)af[i], (float)bf[j], acc[i][j], 0, 0, 0);
+          else
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+        }
     }
   };
 
@@ -386,13 +397,13 @@ gemm_dma_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __r
 #pragma unroll
     for (int j = 0; j < SN; ++j) {
       const int64_t n = n0 + wn * WTN + j * 16 + li;
-      const int64_t mb = m0 + wm * WTM + i * 16 + 4 * lg;
+      const int64_t mb = m0 + wm * WTM + i * 16 + (F32C ? lg : 4 * lg);
       if (n >= N) continue;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t m = mb + v;
+        const int64_t m = mb + (F32C ? 4 * v : v);
         if (m >= M) continue;
-        const double val = acc[i][j][v];
+        const double val = (double)acc[i][j][v];
         if (part != nullptr) {
           part[zoff + m + n * M] = val;
         } else {
@@ -568,12 +579,12 @@ Plan plan_gemm(bool ta, int64_t M, int64_t N, int64_t K, const double* A, int64_
   return p;
 }
 
-template <int ROLE, bool TA, int MT, int NT, int S, int OCC, int WM = 2, int WN = 2>
+template <int ROLE, bool TA, int MT, int NT, int S, int OCC, int WM = 2, int WN = 2, bool F32C = false>
 hipError_t launch_dma(const Plan& p, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
                       const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double* part, const int* gate,
                       hipStream_t s) {
   const dim3 grid((unsigned)((M + MT - 1) / MT), (unsigned)((N + NT - 1) / NT), (unsigned)p.nsplit);
-  hipLaunchKernelGGL((gemm_dma_kernel<ROLE, TA, MT, NT, S, OCC, WM, WN>), grid, dim3(64 * WM * WN), 0, s, M, N, K,
+  hipLaunchKernelGGL((gemm_dma_kernel<ROLE, TA, MT, NT, S, OCC, WM, WN, F32C>), grid, dim3(64 * WM * WN), 0, s, M, N, K,
                      alpha, A, lda, B, ldb, beta, C, ldc, p.kchunk, part, gate);
   return hipGetLastError();
 }
@@ -591,28 +602,29 @@ hipError_t launch_reg(const Plan& p, int64_t M, int64_t N, int64_t K, double alp
 // Ring depth / occupancy / wave grid per DMA tile (measured on gfx950 for the
 // q x b update and the s x b projection): 128x128 uses a 2-slot ring and 8
 // waves (4 x 2 of 32 x 64 for A^T B, 2 x 4 of 64 x 32 for A B), two waves per
-// SIMD; the smaller shapes use 4 waves and a 3-slot ring.
-template <int ROLE, bool TA>
+// SIMD; the smaller shapes use 4 waves and a 3-slot ring.  F32C selects the
+// FP32-arithmetic form of the DMA kernel (the register kernel has none).
+template <int ROLE, bool TA, bool F32C = false>
 hipError_t launch(const Plan& p, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
                   const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double* part, const int* gate,
                   hipStream_t s) {
   if (p.dma) {
     if (p.mt == 16) {
       if constexpr (TA)
-        return launch_dma<ROLE, TA, 16, 16, 3, 8, 1, 1>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
+        return launch_dma<ROLE, TA, 16, 16, 3, 8, 1, 1, F32C>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
     }
     if (p.mt == 32)
-      return launch_dma<ROLE, TA, 32, 32, 3, 4>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
+      return launch_dma<ROLE, TA, 32, 32, 3, 4, 2, 2, F32C>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
     if (p.nt == 16 && p.mt == 128)
-      return launch_dma<ROLE, TA, 128, 16, 3, 4, 2, 1>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
+      return launch_dma<ROLE, TA, 128, 16, 3, 4, 2, 1, F32C>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
     if (p.mt == 128 && p.nt == 128) {
       if (TA)
-        return launch_dma<ROLE, TA, 128, 128, 2, 2, 4, 2>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
-      return launch_dma<ROLE, TA, 128, 128, 2, 2, 2, 4>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
+        return launch_dma<ROLE, TA, 128, 128, 2, 2, 4, 2, F32C>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
+      return launch_dma<ROLE, TA, 128, 128, 2, 2, 2, 4, F32C>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
     }
-    if (p.mt == 128) return launch_dma<ROLE, TA, 128, 64, 3, 2>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
-    if (p.nt == 128) return launch_dma<ROLE, TA, 64, 128, 3, 2>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
-    return launch_dma<ROLE, TA, 64, 64, 3, 3>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
+    if (p.mt == 128) return launch_dma<ROLE, TA, 128, 64, 3, 2, 2, 2, F32C>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
+    if (p.nt == 128) return launch_dma<ROLE, TA, 64, 128, 3, 2, 2, 2, F32C>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
+    return launch_dma<ROLE, TA, 64, 64, 3, 3, 2, 2, F32C>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
   }
   if (p.mt == 128 && p.nt == 128) return launch_reg<ROLE, TA, 128, 128>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
   if (p.mt == 128) return launch_reg<ROLE, TA, 128, 64>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, gate, s);
@@ -624,7 +636,7 @@ hipError_t launch(const Plan& p, int64_t M, int64_t N, int64_t K, double alpha, 
 
 hipError_t gemm_tn(Role role, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
                    const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double* part, size_t part_cap,
-                   const int* gate, hipStream_t s, double flops) {
+                   const int* gate, hipStream_t s, double flops, bool f32) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (!ld_ok(lda) || !ld_ok(ldb)) return hipErrorInvalidValue;
   const Plan p = plan_gemm(true, M, N, K, A, lda, B, ldb, part != nullptr, part_cap, role == ROLE_GRAM && M == N,
@@ -633,7 +645,9 @@ hipError_t gemm_tn(Role role, int64_t M, int64_t N, int64_t K, double alpha, con
   double* pp = p.nsplit > 1 ? part : nullptr;
   const int slot = prof_begin(s);
   hipError_t e;
-  if (role == ROLE_GRAM)
+  if (role == ROLE_GRAM && f32)
+    e = launch<ROLE_GRAM, true, true>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, pp, gate, s);
+  else if (role == ROLE_GRAM)
     e = launch<ROLE_GRAM, true>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, pp, gate, s);
   else if (role == ROLE_CHOL)
     e = launch<ROLE_CHOL, true>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, pp, gate, s);
@@ -656,7 +670,7 @@ hipError_t gemm_tn(Role role, int64_t M, int64_t N, int64_t K, double alpha, con
 
 hipError_t gemm_nn(Role role, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
                    const double* B, int64_t ldb, double beta, double* C, int64_t ldc, const int* gate, hipStream_t s,
-                   double flops) {
+                   double flops, bool f32) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (!ld_ok(lda) || !ld_ok(ldb)) return hipErrorInvalidValue;
   const Plan p = plan_gemm(false, M, N, K, A, lda, B, ldb, false, 0, false, role == ROLE_TRSM || role == ROLE_SMALL);
@@ -668,7 +682,10 @@ hipError_t gemm_nn(Role role, int64_t M, int64_t N, int64_t K, double alpha, con
       e = launch<ROLE_UPDATE, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, gate, s);
       break;
     case ROLE_TRSM:
-      e = launch<ROLE_TRSM, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, gate, s);
+      if (f32)
+        e = launch<ROLE_TRSM, false, true>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, gate, s);
+      else
+        e = launch<ROLE_TRSM, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, gate, s);
       break;
     case ROLE_CHOL:
       e = launch<ROLE_CHOL, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, gate, s);

@@ -534,19 +534,22 @@ int block_rest(int prec, int64_t q, int64_t w, int64_t s, const double* Yj, int6
       MX_RC(stage_operand(prec, q, w, ws.T, ws, sl, ws.cmax, gate, st));
       MX_RC(project_update(prec, q, w, 0, s, ws.T, ws.Hb, ws, sl, ws.hinv, ws.cmax, ws.part, gate, st));
     }
-    // S3/S8 (Gram) and S5/S10 (TRSM) in FP64 on the FP64 block; S4/S9 the
-    // Cholesky factorisation in FP32 arithmetic, whose rounding is far below
-    // the projections' BF16/FP8 rounding that the factors carry anyway.  The
+    // S3/S8 (Gram) and S5/S10 (TRSM) on the FP64 block in FP32 arithmetic
+    // (FP32 products and sums over each workgroup's reduction range, FP64
+    // split sums and results); S4/S9 the Cholesky factorisation in FP32
+    // arithmetic.  Their rounding is far below the projections' BF16/FP8
+    // rounding that the factors carry anyway, and the FP32 Cholesky already
+    // rounds the Gram to FP32.  The
     // strictly lower blocks of the factors' buffers are never written, so
     // they keep the zeros of the cleared workspace for every block of the
     // call's width (a ragged last block lays the buffers out with another
     // leading dimension and clears them).
     MX_TRY(gemm_tn(ROLE_GRAM, w, w, q, 1.0, X, q, X, q, 0.0, ws.W, w, (double*)ws.part, ws.part_cap / 2, gate, st,
-                   (s > 0 ? 2.0 : 1.0) * dw * dw * dq));
+                   (s > 0 ? 2.0 : 1.0) * dw * dw * dq, /*f32=*/true));
     MX_TRY(chol_inv_wide((int)w, ws.W, w, pass == 0 ? ws.LT1 : ws.LT2, pass == 0 ? ws.XT1 : ws.XT2, ws.Rjj, ws.status,
                          pass + 1, blk, st, /*f32=*/true, /*lower_zero=*/w == ws.b));
     MX_TRY(gemm_nn(ROLE_TRSM, q, w, w, 1.0, X, q, pass == 0 ? ws.XT1 : ws.XT2, w, 0.0, pass == 0 ? ws.T : sl.Qj, q,
-                   gate, st, dw * dw * dq));
+                   gate, st, dw * dw * dq, /*f32=*/true));
   }
   // S11 R_jj = Lb^T L^T, S12 H = H + Hb L^T, in FP64; then the fallback
   // (a breakdown redoes the block by CGS2), R (FP32) and the finished columns.
