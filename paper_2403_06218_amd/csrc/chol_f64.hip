@@ -164,34 +164,21 @@ chol_inv_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __rest
       T a[16];
 #pragma unroll
       for (int j = 0; j < 16; ++j) a[j] = (lane < 16 && j <= lane) ? sA[(c0 + lane) * kCLD + c0 + j] : T(0);
-      T lii, linv;
-      const bool ok = wave_chol<T, 16>(a, lii, linv, lane);
+      // The factor and X_pp = L_pp^{-1} (row i: linv_i times row i of
+      // U^{-1}, formed during the factorisation), X stored transposed above
+      // the diagonal.
+      T lii, linv, y[16];
+      const bool ok = wave_chol_inv<T, 16>(a, y, lii, linv, lane);
       if (lane == 0 && !ok) bad = 1;
       if (lane < 16) {
 #pragma unroll
         for (int j = 0; j < 16; ++j)
-          if (j < lane) sA[(c0 + lane) * kCLD + c0 + j] = a[j];
+          if (j < lane) {
+            sA[(c0 + lane) * kCLD + c0 + j] = a[j];
+            sA[(c0 + j) * kCLD + c0 + lane] = y[j] * linv;
+          }
         sA[(c0 + lane) * kCLD + c0 + lane] = lii;
         sD[c0 + lane] = linv;
-      }
-      // X_pp = L_pp^{-1} in registers: with M = D^{-1} L (row i scaled by
-      // 1 / L_ii, unit diagonal), X = M^{-1} D^{-1}.  Lane i owns row i of
-      // M^{-1}, formed right-looking from the identity: at step k row k is
-      // final and is broadcast, and every row i > k subtracts M_ik times it.
-      T xr[16];
-#pragma unroll
-      for (int j = 0; j < 16; ++j) xr[j] = (j == lane) ? T(1) : T(0);
-#pragma unroll
-      for (int k = 0; k < 15; ++k) {
-        const T mik = (lane > k) ? a[k] * linv : T(0);
-#pragma unroll
-        for (int j = 0; j <= k; ++j) xr[j] -= mik * row_bcast(xr[j], k);
-      }
-      // X(i, j) = (M^{-1})_ij / L_jj, stored transposed above the diagonal.
-#pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const T djinv = row_bcast(linv, j);
-        if (lane < 16 && j < lane) sA[(c0 + j) * kCLD + c0 + lane] = xr[j] * djinv;
       }
     } else {
       // Tasks of this step, one per wave 1..7 (at most 7 exist): tiles t =
@@ -288,8 +275,8 @@ unsigned grid_for(int64_t total) {
 }  // namespace
 
 // The same contract for b <= 16 in one wave, registers only: lane i < 16
-// holds row i of W, factors it with wave_chol, forms row i of X = L^{-1}
-// as in the diagonal blocks above, and writes column i of LT and of XT.
+// holds row i of W, factors it and forms row i of X = L^{-1} with
+// wave_chol_inv, and writes column i of LT and of XT.
 __global__ void __launch_bounds__(64)
 chol_inv16_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __restrict__ LT, double* __restrict__ XT,
                   int64_t ldo, int* status, int code, int blk) {
@@ -299,24 +286,14 @@ chol_inv16_kernel(int b, const double* __restrict__ W, int64_t ldw, double* __re
 #pragma unroll
   for (int j = 0; j < 16; ++j)
     a[j] = (lane < b && j <= lane) ? W[lane + (int64_t)j * ldw] : ((lane == j) ? 1.0 : 0.0);
-  double lii, linv;
-  const bool ok = wave_chol<double, 16>(a, lii, linv, lane);
-  double xr[16];
-#pragma unroll
-  for (int j = 0; j < 16; ++j) xr[j] = (j == lane) ? 1.0 : 0.0;
-#pragma unroll
-  for (int k = 0; k < 15; ++k) {
-    const double mik = (lane > k) ? a[k] * linv : 0.0;
-#pragma unroll
-    for (int j = 0; j <= k; ++j) xr[j] -= mik * row_bcast(xr[j], k);
-  }
-  // LT(j, i) = L(i, j) and XT(j, i) = X(i, j) = (M^{-1})_ij / L_jj.
+  double lii, linv, y[16];
+  const bool ok = wave_chol_inv<double, 16>(a, y, lii, linv, lane);
+  // LT(j, i) = L(i, j) and XT(j, i) = X(i, j) = linv_i (U^{-1})_ij.
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
-    const double djinv = row_bcast(linv, j);
     if (lane < b && j < b) {
       LT[j + (int64_t)lane * ldo] = (j < lane) ? a[j] : ((j == lane) ? lii : 0.0);
-      XT[j + (int64_t)lane * ldo] = (j < lane) ? xr[j] * djinv : ((j == lane) ? linv : 0.0);
+      XT[j + (int64_t)lane * ldo] = (j < lane) ? y[j] * linv : ((j == lane) ? linv : 0.0);
     }
   }
   if (lane == 0 && !ok) {
@@ -350,7 +327,9 @@ hipError_t chol_inv(int b, const double* W, int64_t ldw, double* LT, double* XT,
 //   L11 L11^T = W11;  U12 = L21^T = X11 W12;  S = W22 - U12^T U12;  L22 L22^T = S;
 //   X21^T = -X11^T U12 X22^T.
 // Writes LT = [L11^T U12; 0 L22^T] and XT = [X11^T X21^T; 0 X22^T] (ld b).
-// W's trailing block is overwritten by S; tmp holds b1 x b2 doubles.
+// W's trailing block is overwritten by S; tmp holds b1 x b2 doubles.  With f32
+// the two diagonal factorisations and the four products take FP32 arithmetic
+// (FP64 data throughout).
 hipError_t chol_inv_wide(int b, double* W, int64_t ldw, double* LT, double* XT, double* tmp, int* status, int code,
                          int blk, hipStream_t s, bool f32, bool lower_zero) {
   if (b <= kCB) return chol_inv(b, W, ldw, LT, XT, status, code, blk, s, f32);
@@ -365,20 +344,21 @@ hipError_t chol_inv_wide(int b, double* W, int64_t ldw, double* LT, double* XT, 
   if ((e = chol_inv_ld(b1, W, ldw, LT, XT, b, status, code, blk, f32, s)) != hipSuccess) return e;
   // U12 = X11 W12 = (XT11)^T W12.
   if ((e = gemm_tn(ROLE_CHOL, b1, b2, b1, 1.0, XT, b, W12, ldw, 0.0, U12, b, nullptr, 0, status, s,
-                   d1 * d1 * d2)) != hipSuccess)
+                   d1 * d1 * d2, f32)) != hipSuccess)
     return e;
   // S = W22 - U12^T U12 (in place).
   if ((e = gemm_tn(ROLE_CHOL, b2, b2, b1, -1.0, U12, b, U12, b, 1.0, W22, ldw, nullptr, 0, status, s,
-                   2.0 * d1 * d2 * d2)) != hipSuccess)
+                   2.0 * d1 * d2 * d2, f32)) != hipSuccess)
     return e;
   if ((e = chol_inv_ld(b2, W22, ldw, LT + b1 + (int64_t)b1 * b, XT + b1 + (int64_t)b1 * b, b, status, code, blk,
                        f32, s)) != hipSuccess)
     return e;
   // X21^T = -(XT11 U12) XT22.
-  if ((e = gemm_nn(ROLE_CHOL, b1, b2, b1, 1.0, XT, b, U12, b, 0.0, tmp, b1, status, s, d1 * d1 * d2)) != hipSuccess)
+  if ((e = gemm_nn(ROLE_CHOL, b1, b2, b1, 1.0, XT, b, U12, b, 0.0, tmp, b1, status, s, d1 * d1 * d2, f32)) !=
+      hipSuccess)
     return e;
   if ((e = gemm_nn(ROLE_CHOL, b1, b2, b2, -1.0, tmp, b1, XT + b1 + (int64_t)b1 * b, b, 0.0, X12, b, status, s,
-                   2.0 * d1 * d2 * d2)) != hipSuccess)
+                   2.0 * d1 * d2 * d2, f32)) != hipSuccess)
     return e;
   // Strictly lower blocks of LT and XT (nothing else writes them, so a
   // caller whose buffers start zero need not clear them again).

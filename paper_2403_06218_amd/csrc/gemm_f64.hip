@@ -649,6 +649,8 @@ hipError_t gemm_tn(Role role, int64_t M, int64_t N, int64_t K, double alpha, con
     e = launch<ROLE_GRAM, true, true>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, pp, gate, s);
   else if (role == ROLE_GRAM)
     e = launch<ROLE_GRAM, true>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, pp, gate, s);
+  else if (role == ROLE_CHOL && f32)
+    e = launch<ROLE_CHOL, true, true>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, pp, gate, s);
   else if (role == ROLE_CHOL)
     e = launch<ROLE_CHOL, true>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, pp, gate, s);
   else if (role == ROLE_APROD)
@@ -688,7 +690,10 @@ hipError_t gemm_nn(Role role, int64_t M, int64_t N, int64_t K, double alpha, con
         e = launch<ROLE_TRSM, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, gate, s);
       break;
     case ROLE_CHOL:
-      e = launch<ROLE_CHOL, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, gate, s);
+      if (f32)
+        e = launch<ROLE_CHOL, false, true>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, gate, s);
+      else
+        e = launch<ROLE_CHOL, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, gate, s);
       break;
     case ROLE_APROD:
       e = launch<ROLE_APROD, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, gate, s);
@@ -697,7 +702,10 @@ hipError_t gemm_nn(Role role, int64_t M, int64_t N, int64_t K, double alpha, con
       e = launch<ROLE_SVD, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, gate, s);
       break;
     default:
-      e = launch<ROLE_SMALL, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, gate, s);
+      if (f32)
+        e = launch<ROLE_SMALL, false, true>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, gate, s);
+      else
+        e = launch<ROLE_SMALL, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, gate, s);
       break;
   }
   prof_end(slot, role, s, flops, bytes);

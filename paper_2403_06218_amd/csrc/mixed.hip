@@ -551,10 +551,13 @@ int block_rest(int prec, int64_t q, int64_t w, int64_t s, const double* Yj, int6
     MX_TRY(gemm_nn(ROLE_TRSM, q, w, w, 1.0, X, q, pass == 0 ? ws.XT1 : ws.XT2, w, 0.0, pass == 0 ? ws.T : sl.Qj, q,
                    gate, st, dw * dw * dq, /*f32=*/true));
   }
-  // S11 R_jj = Lb^T L^T, S12 H = H + Hb L^T, in FP64; then the fallback
-  // (a breakdown redoes the block by CGS2), R (FP32) and the finished columns.
+  // S11 R_jj = Lb^T L^T in FP64, S12 H = H + Hb L^T in FP32 arithmetic on
+  // FP64 data (R is returned in FP32); then the fallback (a breakdown redoes
+  // the block by CGS2), R (FP32) and the finished columns.
   MX_TRY(gemm_nn(ROLE_SMALL, w, w, w, 1.0, ws.LT2, w, ws.LT1, w, 0.0, ws.Rjj, w, gate, st, dw * dw * dw));
-  if (s > 0) MX_TRY(gemm_nn(ROLE_SMALL, s, w, w, 1.0, ws.Hb, ws.rp, ws.LT1, w, 1.0, sl.H, ws.rp, gate, st, dw * ds));
+  if (s > 0)
+    MX_TRY(gemm_nn(ROLE_SMALL, s, w, w, 1.0, ws.Hb, ws.rp, ws.LT1, w, 1.0, sl.H, ws.rp, gate, st, dw * ds,
+                   /*f32=*/true));
   MX_TRY(block_fallback(q, w, s, Yj, ldy, Q32, ldq, ws, sl, blk, info, flags, st));
   if (s > 0) {
     hipLaunchKernelGGL(to_f32_kernel, dim3(grid_of(s * w)), dim3(256), 0, st, s, w, sl.H, ws.rp, R32 + s * ldr, ldr,

@@ -109,4 +109,39 @@ __device__ __forceinline__ bool wave_chol(T (&a)[WP], T& lii, T& linv, int lane)
   return ok;
 }
 
+// wave_chol that also forms the inverse: on return lane i < WP additionally
+// holds y[j] = (U^{-1})(i, j) for j <= i (zero above), so that
+// L^{-1}(i, j) = linv * y[j] with this lane's linv (L^{-1} = D^{-1/2} U^{-1}).
+// Row k of U^{-1} is final once step k begins (it has received the updates
+// of steps 0 .. k-1), and at step k every row i > k subtracts u_ik times it;
+// these updates sit beside the step's division, off its dependent chain.
+template <typename T, int WP>
+__device__ __forceinline__ bool wave_chol_inv(T (&a)[WP], T (&y)[WP], T& lii, T& linv, int lane) {
+  bool ok = true;
+  T dmine = T(1);
+#pragma unroll
+  for (int j = 0; j < WP; ++j) y[j] = (j == lane) ? T(1) : T(0);
+#pragma unroll
+  for (int k = 0; k < WP; ++k) {
+    const T d = small_bcast<WP>(a[k], k);
+    ok = ok && (d > T(0));
+    const T r = T(1) / d;
+    const T c = a[k];
+    const T u = c * r;
+#pragma unroll
+    for (int j = k + 1; j < WP; ++j) a[j] -= u * small_bcast<WP>(c, j);
+    const T uk = (lane > k) ? u : T(0);
+#pragma unroll
+    for (int j = 0; j <= k; ++j) y[j] -= uk * small_bcast<WP>(y[j], k);
+    dmine = (lane == k) ? d : dmine;
+    a[k] = u;
+  }
+  const T s = sqrt(dmine);
+  lii = s;
+  linv = T(1) / s;
+#pragma unroll
+  for (int j = 0; j < WP; ++j) a[j] *= small_bcast<WP>(s, j);
+  return ok;
+}
+
 }  // namespace cqr
