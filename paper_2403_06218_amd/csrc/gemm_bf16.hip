@@ -72,8 +72,16 @@ __device__ __forceinline__ void stage_barrier() {
 }
 
 // Tile height of the wide kernel: 256 for projections with at least 12288
-// rows of output (measured: 5-15% faster there, slower for fewer rows).
-int wide_mt(int role, int64_t M) { return (role == ROLE_PROJ && M >= 12288) ? 256 : 128; }
+// rows of output (measured: 5-15% faster there, slower for fewer rows), and
+// for BF16 updates of at least 12288 rows, whose reduction the caller then
+// splits in two through FP32 partial sums so that the half as many row tiles
+// still occupy every CU (measured at q = 32768: the BF16 updates 83 -> 70 ms
+// per factorisation, the extra reduction +9 ms; the FP8 updates 46 -> 38 ms
+// with the same +9 ms, so they keep the 128-row tile).
+int wide_mt(int role, int64_t M, bool fp8) {
+  if (M < 12288) return 128;
+  return (role == ROLE_PROJ || !fp8) ? 256 : 128;
+}
 
 // Byte offset of chunk c (8 k values) of column x in a stage.
 __device__ __forceinline__ int chunk_off(int c, int x) { return x * 128 + 16 * (c ^ ((x >> 1) & 7)); }
@@ -228,7 +236,8 @@ gemm_bf16_kernel(int64_t M, int64_t N, int64_t K, float alpha, const __bf16* __r
 
 // 128 x 256 tile with 2 x 4 waves (64 x 64 per wave; MT_ = 256: 256 x 256
 // with 128 x 64 per wave, for the projections of the later blocks, whose
-// s x b output needs few splits) and the loads split by wave: waves 0-3 copy A
+// s x b output needs few splits, and for the BF16 updates, split in two along
+// k) and the loads split by wave: waves 0-3 copy A
 // (the row panel, unique to the workgroup and streamed from HBM, loaded
 // non-temporal), waves 4-7 copy B (shared by all workgroups, served by L2),
 // each into a ring of SA / SB slots, so each wave's vmcnt counts only its own
@@ -516,8 +525,8 @@ hipError_t launch_bf16_tile(int64_t M, int64_t N, int64_t K, float alpha, const 
   // A tiled A is read by the wide kernel only (columns past M or N are
   // clamped and not stored, so any shape fits it).
   if ((M > 64 && N > 128) || a_blk > 0) {
-    if constexpr (ROLE == ROLE_PROJ) {
-      if (wide_mt(ROLE, M) == 256) {
+    {
+      if (wide_mt(ROLE, M, false) == 256) {
         const dim3 grid((unsigned)((M + 255) / 256), (unsigned)((N + 255) / 256), (unsigned)nsplit);
         hipLaunchKernelGGL((gemm_lp_wide_kernel<__bf16, ROLE, OUT, 2, 2, 256>), grid, dim3(512), 0, s, M, N, K, alpha,
                            A, lda, a_blk, B, ldb, beta, C, ldc, kchunk, part, (const float*)nullptr, (const float*)nullptr,
@@ -544,7 +553,7 @@ hipError_t launch_bf16_tile(int64_t M, int64_t N, int64_t K, float alpha, const 
 
 int64_t bf16_tiles(int role, int64_t M, int64_t N, bool force_wide) {
   const bool wide = (M > 64 && N > 128) || force_wide;
-  const int64_t mt = wide ? wide_mt(role, M) : (M > 64 ? 128 : 64), nt = wide ? 256 : (N > 64 ? 128 : 64);
+  const int64_t mt = wide ? wide_mt(role, M, false) : (M > 64 ? 128 : 64), nt = wide ? 256 : (N > 64 ? 128 : 64);
   return ((M + mt - 1) / mt) * ((N + nt - 1) / nt);
 }
 
@@ -635,7 +644,7 @@ hipError_t gemm_fp8_tn(Role role, int64_t M, int64_t N, int64_t K, float alpha, 
   if (!gemm_fp8_supported(A, a_blk ? 16 : lda, B, ldb, K)) return hipErrorInvalidValue;
   if (a_blk < 0 || a_blk % (128 * 128) != 0) return hipErrorInvalidValue;
   // The wide tile (columns past N are clamped and not stored), 128 or 256 rows.
-  const int mt = wide_mt(role, M);
+  const int mt = wide_mt(role, M, true);
   int nsplit = 1;
   if (part != nullptr) {
     const int64_t tiles = ((M + mt - 1) / mt) * ((N + 255) / 256);

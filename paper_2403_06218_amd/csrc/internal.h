@@ -57,7 +57,9 @@ hipError_t gemm_nn(Role role, int64_t M, int64_t N, int64_t K, double alpha, con
 
 // BF16 GEMM with FP32 accumulation: C (M x N) = alpha * A^T B + beta * C with
 // A (K x M) and B (K x N) BF16, k-contiguous.  C is FP64 when c_is_f64, else
-// FP32 (then split over K through `part`, capacity part_cap floats).
+// FP32.  With `part` non-null the reduction over K may be split through FP32
+// partial sums in `part` (capacity part_cap floats), added into C in split
+// order by a second launch.
 // Requires 16-byte aligned A and B, lda and ldb multiples of 8, K a multiple of 64.
 // A is column-major (lda) when a_blk == 0, else tiled: columns in blocks of
 // 128, each block a_blk elements holding its k-stages (64 k, 128 bytes per

@@ -511,10 +511,11 @@ int project_update(int prec, int64_t q, int64_t w, int64_t c0, int64_t c1, doubl
     hipLaunchKernelGGL(to_bf16_kernel, cvt_grid(kp, w), dim3(256), 0, st, m, kp, w, Hd + c0, ws.rp, sl.H16 + c0,
                        ws.rp, gate);
     MX_TRY(hipGetLastError());
-    // X -= P H  (A = P^T stored k-contiguous)
+    // X -= P H  (A = P^T stored k-contiguous); for at least 12288 rows the
+    // 256-row tile with the reduction split in two through FP32 partial sums.
     const __bf16* pt = ws.blk_pt ? ws.P16T + c0 * 128 : ws.P16T + c0;
     MX_TRY(gemm_bf16_tn(ROLE_UPDATE, q, w, kp, -1.0f, pt, ws.rp, ws.blk_pt, sl.H16 + c0, ws.rp, 1.0f, X, q, true,
-                        nullptr, 0, gate, st, flops));
+                        part, ws.part_cap, gate, st, flops));
   }
   return CQR_OK;
 }
