@@ -405,7 +405,9 @@ gemm_dma_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __r
         if (m >= M) continue;
         const double val = (double)acc[i][j][v];
         if (part != nullptr) {
-          part[zoff + m + n * M] = val;
+          // FP32 sums are stored as FP32: the partial-sum traffic halves.
+          if constexpr (F32C) reinterpret_cast<float*>(part)[zoff + m + n * M] = acc[i][j][v];
+          else part[zoff + m + n * M] = val;
         } else {
           double c = alpha * val;
           if (beta != 0.0) c += beta * C[m + n * ldc];
@@ -418,9 +420,11 @@ gemm_dma_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __r
 // C = alpha * sum_z part[z] + beta * C, deterministic: a workgroup covers 64
 // consecutive outputs with 4 groups of 64 threads; group g sums its quarter of
 // the splits in split order (16 loads in flight), and the 4 group sums are
-// added in group order.
+// added in group order.  P: the partial sums' type (FP64, or FP32 from the
+// FP32-arithmetic kernels); the sums are FP64.
+template <typename P>
 __global__ void __launch_bounds__(256)
-splitk_reduce_kernel(int64_t M, int64_t N, int nsplit, const double* __restrict__ part, double alpha, double beta,
+splitk_reduce_kernel(int64_t M, int64_t N, int nsplit, const P* __restrict__ part, double alpha, double beta,
                      double* C, int64_t ldc, const int* __restrict__ gate) {
   if (gate != nullptr && *gate != 0) return;
   __shared__ double red[4][64];
@@ -436,11 +440,11 @@ splitk_reduce_kernel(int64_t M, int64_t N, int nsplit, const double* __restrict_
       for (; z + 16 <= z1; z += 16) {
         double v[16];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) v[u] = part[(int64_t)(z + u) * total + idx];
+        for (int u = 0; u < 16; ++u) v[u] = (double)part[(int64_t)(z + u) * total + idx];
 #pragma unroll
         for (int u = 0; u < 16; ++u) s += v[u];
       }
-      for (; z < z1; ++z) s += part[(int64_t)z * total + idx];
+      for (; z < z1; ++z) s += (double)part[(int64_t)z * total + idx];
     }
     red[g][o] = s;
     __syncthreads();
@@ -662,11 +666,19 @@ hipError_t gemm_tn(Role role, int64_t M, int64_t N, int64_t K, double alpha, con
   const int64_t total = M * N;
   int64_t blocks = (total + 63) / 64;
   if (blocks > 8192) blocks = 8192;
+  // The FP32-arithmetic DMA instances (ROLE_GRAM, ROLE_CHOL with f32) store
+  // FP32 partial sums; the register kernel, which has no FP32 form, FP64.
+  const bool f32part = f32 && p.dma && (role == ROLE_GRAM || role == ROLE_CHOL);
   const int slot2 = prof_begin(s);
-  hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, s, M, N, p.nsplit, part, alpha,
-                     beta, C, ldc, gate);
+  if (f32part)
+    hipLaunchKernelGGL(splitk_reduce_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s, M, N, p.nsplit,
+                       reinterpret_cast<const float*>(part), alpha, beta, C, ldc, gate);
+  else
+    hipLaunchKernelGGL(splitk_reduce_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, M, N, p.nsplit,
+                       (const double*)part, alpha, beta, C, ldc, gate);
   e = hipGetLastError();
-  prof_end(slot2, ROLE_REDUCE, s, 0.0, 8.0 * (double)total * (p.nsplit + (beta != 0.0 ? 2 : 1)));
+  prof_end(slot2, ROLE_REDUCE, s, 0.0,
+           (double)total * ((f32part ? 4.0 : 8.0) * p.nsplit + 8.0 * (beta != 0.0 ? 2 : 1)));
   return e;
 }
 

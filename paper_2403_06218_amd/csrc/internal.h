@@ -41,8 +41,8 @@ void prof_end(int slot, int role, hipStream_t s, double flops, double bytes);
 
 // C = alpha * A^T B + beta * C;  A: K x M (lda), B: K x N (ldb), C: M x N (ldc).
 // Split over K through `part` (capacity part_cap doubles) when it pays.
-// f32 (ROLE_GRAM and ROLE_CHOL only): FP32 products and per-split sums, FP64
-// data and split reduction.
+// f32 (ROLE_GRAM and ROLE_CHOL only): FP32 products and per-split sums (stored
+// as FP32 in `part`), FP64 data and split reduction.
 hipError_t gemm_tn(Role role, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
                    const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double* part,
                    size_t part_cap, const int* gate, hipStream_t s, double flops, bool f32 = false);
