@@ -643,7 +643,13 @@ hipError_t gemm_tn(Role role, int64_t M, int64_t N, int64_t K, double alpha, con
                    const int* gate, hipStream_t s, double flops, bool f32) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (!ld_ok(lda) || !ld_ok(ldb)) return hipErrorInvalidValue;
-  const Plan p = plan_gemm(true, M, N, K, A, lda, B, ldb, part != nullptr, part_cap, role == ROLE_GRAM && M == N,
+  // The FP32-arithmetic Gram splits its reduction at most 64 ways (measured
+  // on the q x 256 Gram at q = 32768: 64 splits of 512 rows 14.7 ms per
+  // low-precision factorisation, 128 of 256 rows 15.7 ms; 82, 96 and 158
+  // splits of 400, 352 and 208 rows 19.4-20.6 ms).
+  size_t cap = part_cap;
+  if (f32 && role == ROLE_GRAM && (size_t)64 * (size_t)(M * N) < cap) cap = (size_t)64 * (size_t)(M * N);
+  const Plan p = plan_gemm(true, M, N, K, A, lda, B, ldb, part != nullptr, cap, role == ROLE_GRAM && M == N,
                            false, role == ROLE_APROD);
   const double bytes = 8.0 * ((double)K * M + (double)K * N + (double)M * N * (beta != 0.0 ? 2.0 : 1.0));
   double* pp = p.nsplit > 1 ? part : nullptr;
